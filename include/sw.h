@@ -1,0 +1,215 @@
+/*
+ * sw.h -- C ABI of the MI355X Swendsen-Wang engine (libswmc.so).
+ *
+ * The engine runs the Swendsen-Wang multi-cluster update of Komura & Okabe,
+ * "CUDA programs for GPU computing of Swendsen-Wang multi-cluster spin flip
+ * algorithm: 2D and 3D Ising, Potts, and XY models", for
+ *   Ising   (Sec. 1, Eq. (1)),  states int8 +1/-1,
+ *   Potts   (Sec. 1, Eq. (2)),  states uint8 in [0,q)  (paper: 1..q),
+ *   XY      (Sec. 1, Eq. (3)),  states float angles in [0, (float)2pi),
+ * on 2D square and 3D simple-cubic lattices of linear size L with periodic
+ * boundaries.  One sweep is the three steps of Sec. 2: (1) active-bond
+ * generation, (2) cluster labelling (label equivalence, fixed point = minimum
+ * site index), (3) every cluster set to a random state.  Every step runs in
+ * HIP kernels on one GPU.
+ *
+ * Conventions shared by every call:
+ *   site index  i = x + L*(y + L*z), x fastest; N = L^dim.
+ *   bond byte   bit mu (0=x,1=y,2=z) = bond between i and its +mu neighbour.
+ *   labels      int32, minimum site index of the cluster.
+ *   random      Philox4x32-10; word w of stream (tag, sweep n) of replica r
+ *               is lane w%4 of Philox(counter=(w/4, n, tag, r),
+ *               key=(seed mod 2^32, seed div 2^32)); tags: bond x/y/z = 0/1/2,
+ *               cluster = 3, global = 4, init = 5.  The sweep index n is
+ *               0-based and cumulative over calls.
+ *   couplings   J = k_B = 1, beta = 1/T.  Bond probability: Ising
+ *               1-exp(-2 beta) (Sec. 2, step (1)), Potts 1-exp(-beta), XY
+ *               1-exp(-2 beta sigma_i sigma_j) on the projections
+ *               sigma = cos(theta - phi) onto a random direction phi drawn
+ *               once per sweep (Sec. 2, embedded-cluster paragraph).
+ *
+ * Errors: every int-returning call returns 0 (or a count) on success and a
+ * negative SW_E_* code on failure; sw_last_error() gives a message for the
+ * calling thread.  Handles are not thread-safe: one thread per handle.
+ * All host pointers are owned by the caller and must hold the stated number
+ * of elements; calls that take them are synchronous.  Device memory is owned
+ * by the library and freed by sw_destroy / sw_batch_destroy.
+ */
+#ifndef SW_H
+#define SW_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum sw_model { SW_ISING = 0, SW_POTTS = 1, SW_XY = 2 };
+
+enum sw_status {
+    SW_OK = 0,
+    SW_E_INVALID = -1, /* bad argument (model, dim, L, q, beta, sizes, NULL) */
+    SW_E_NOMEM = -2,   /* device or host allocation failed */
+    SW_E_DEVICE = -3,  /* HIP runtime error (message in sw_last_error) */
+    SW_E_NOCONV = -4,  /* labelling did not reach its fixed point within the cap */
+    SW_E_BUSY = -5,    /* serving queue full / slot budget exhausted */
+    SW_E_NOTFOUND = -6 /* unknown job id */
+};
+
+typedef struct sw_ctx *sw_handle;
+
+/* Cluster statistics of the last labelling (Sec. 2, step (2)). */
+typedef struct {
+    int64_t n_clusters;  /* number of clusters */
+    int64_t max_cluster; /* size of the largest cluster */
+    int64_t sum_c2;      /* sum over clusters of size^2 (improved estimator of M^2) */
+} sw_cluster_stats;
+
+/* Observables of one configuration (Sec. 2: M = sum s, energy of Eq. (1);
+ * Eq. (5) for the Potts M^2).  `sweep` = number of sweeps done before the
+ * configuration was measured (the configuration entering that sweep). */
+typedef struct {
+    int64_t sweep;
+    double energy; /* H with J = 1 */
+    double mag;    /* Ising: M = sum s; Potts: sqrt(M^2); XY: |(sum cos, sum sin)| */
+    double mag2;   /* M^2 (Potts: Eq. (5)) */
+    double mx, my; /* Ising: (M, 0); Potts: (0, 0); XY: (sum cos, sum sin) */
+} sw_record;
+
+/* --- plain form: one lattice per handle, one launch per kernel ------------ */
+
+/* Create a lattice and give it a hot start (every state drawn from the INIT
+ * stream; the paper's spinset kernel).  model: SW_ISING (q ignored, use 2),
+ * SW_POTTS (2 <= q <= 256), SW_XY (q ignored, use 0); dim 2 or 3; L >= 3 and
+ * L^dim <= 2^31 - 1; beta >= 0 and finite.  Replica 0.  NULL on error. */
+sw_handle sw_create(int model, int dim, int L, int q, double beta, uint64_t seed);
+
+/* As sw_create with an explicit replica index (fourth Philox counter word). */
+sw_handle sw_create_replica(int model, int dim, int L, int q, double beta, uint64_t seed,
+                            uint32_t replica);
+
+/* Run n >= 0 sweeps.  Before each sweep the configuration is measured into
+ * the record series (when measuring is on, the default).  Synchronous. */
+int sw_sweep(sw_handle h, int64_t n);
+
+/* Averages over the recorded series since the last sw_reset_measure:
+ * m2 = <(M/N)^2>, m4 = <(M/N)^4>, energy = <E>/N (any pointer may be NULL),
+ * and the cluster statistics of the last labelling (zeros before any sweep).
+ * With no records the current configuration alone is measured. */
+int sw_measure(sw_handle h, double *m2, double *m4, double *energy, sw_cluster_stats *cs);
+
+/* Drop the recorded series (the paper's discarded MCS). */
+int sw_reset_measure(sw_handle h);
+
+/* Copy up to `max` records (oldest first) into `out`; returns the count. */
+int64_t sw_series(sw_handle h, sw_record *out, int64_t max);
+
+/* Turn per-sweep measurement on (1, default) or off (0). */
+int sw_set_measure(sw_handle h, int on);
+
+/* Release all device memory of the handle.  NULL is ignored. */
+void sw_destroy(sw_handle h);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char *sw_last_error(void);
+
+/* --- state access (checkpoint / parity hooks) ----------------------------- */
+
+/* Number of sweeps done so far (the next sweep's index n). */
+int64_t sw_sweep_index(sw_handle h);
+/* Set the next sweep's index (resume a stream position; 0 <= n < 2^32). */
+int sw_set_sweep_index(sw_handle h, int64_t n);
+/* Copy the N states out / in (int8, uint8 or float by model).  sw_set_state
+ * rejects out-of-range states (Ising not +1/-1, Potts >= q, XY outside
+ * [0, (float)2pi) or NaN) with SW_E_INVALID. */
+int sw_get_state(sw_handle h, void *host_state);
+int sw_set_state(sw_handle h, const void *host_state);
+/* Minimum-index labels (N int32) and bond bytes (N uint8) of the last sweep. */
+int sw_get_labels(sw_handle h, int32_t *host_labels);
+int sw_get_bonds(sw_handle h, uint8_t *host_bonds);
+/* Lattice parameters of a handle (any pointer may be NULL). */
+int sw_info(sw_handle h, int *model, int *dim, int *L, int *q, double *beta, uint64_t *seed,
+            uint32_t *replica);
+
+/* --- batched form: many lattices of uneven size in one launch ------------- */
+
+typedef struct sw_batch_s *sw_batch;
+
+/* One lattice of a batch (same rules as sw_create_replica). */
+typedef struct {
+    int model, dim, L, q;
+    double beta;
+    uint64_t seed;
+    uint32_t replica;
+} sw_job_desc;
+
+/* Create n >= 1 lattices that sweep together: every kernel launch covers the
+ * tiles of all lattices of one (model, dim) group, and chunks of sweeps are
+ * replayed from a captured HIP graph.  NULL on error. */
+sw_batch sw_batch_create(const sw_job_desc *jobs, int n);
+
+/* Run n sweeps on every member.  Each member's trajectory is identical to a
+ * plain handle with the same parameters. */
+int sw_batch_sweep(sw_batch b, int64_t n);
+
+/* Run counts[j] sweeps on member j (0 = idle) in the same batched launches. */
+int sw_batch_sweep_counts(sw_batch b, const int64_t *counts);
+
+/* Number of members; a handle that views member j (state access, measure,
+ * series; do not sw_destroy it, and sw_sweep on it runs that member alone). */
+int sw_batch_size(sw_batch b);
+sw_handle sw_batch_member(sw_batch b, int j);
+
+/* Sweeps replayed per captured graph (default chosen by the tuner). */
+int sw_batch_set_chunk(sw_batch b, int sweeps_per_graph);
+
+void sw_batch_destroy(sw_batch b);
+
+/* --- served form: continuous batching of submitted jobs ------------------- */
+
+typedef struct sw_server_s *sw_server;
+
+/* A job: lattice parameters plus the number of sweeps to run. */
+typedef struct {
+    sw_job_desc lattice;
+    int64_t sweeps;
+} sw_job;
+
+/* Result of a finished job. */
+typedef struct {
+    int64_t id;
+    int status;          /* 0 = done, SW_E_* on failure */
+    int64_t sweeps;      /* sweeps run */
+    double submit_s;     /* server clock at submission, seconds */
+    double start_s;      /* admitted to the device */
+    double finish_s;     /* last sweep completed */
+    double m2, m4, energy; /* averages over all sweeps of the job */
+} sw_job_result;
+
+/* Start a server whose resident lattices may use at most hbm_budget_bytes of
+ * device memory and at most max_active jobs at once; chunk = sweeps per
+ * scheduling tick.  NULL on error. */
+sw_server sw_server_create(int64_t hbm_budget_bytes, int max_active, int chunk);
+
+/* Queue a job; returns its id (>= 0) or SW_E_*.  Jobs whose footprint exceeds
+ * the whole budget are rejected with SW_E_INVALID. */
+int64_t sw_server_submit(sw_server s, const sw_job *job);
+
+/* One scheduling tick: admit queued jobs that fit, run one chunk of sweeps
+ * on every active job in batched launches, retire finished jobs.  Returns
+ * the number of jobs still queued or active. */
+int64_t sw_server_step(sw_server s);
+
+/* Copy the result of finished job `id` (SW_E_NOTFOUND if unknown, 1 if not
+ * finished yet, 0 when copied).  With state != NULL the final configuration
+ * is copied too (N states). */
+int sw_server_poll(sw_server s, int64_t id, sw_job_result *out, void *state);
+
+/* Device bytes one job of this shape needs while resident. */
+int64_t sw_footprint(int model, int dim, int L, int q);
+
+void sw_server_destroy(sw_server s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

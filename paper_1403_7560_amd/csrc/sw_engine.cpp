@@ -1,0 +1,1036 @@
+// sw_engine.cpp -- host runtime behind the C ABI in include/sw.h.
+//
+// Owns device memory, builds the per-lattice descriptors and tile maps the
+// kernels read, drives the plain form (one lattice, one launch per kernel),
+// the batched form (all lattices of a (model, dim) group in one launch, chunks
+// of sweeps replayed from a captured HIP graph) and the served form
+// (continuous batching of submitted jobs under an HBM budget).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/sw.h"
+#include "sw_internal.h"
+
+using namespace swmc;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHK(x)                                                                        \
+    do {                                                                                 \
+        hipError_t e_ = (x);                                                             \
+        if (e_ != hipSuccess)                                                            \
+            return fail(SW_E_DEVICE, std::string(#x) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+size_t state_bytes(int model) { return model == XY ? 4 : 1; }
+
+double now_s()
+{
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+// Bond threshold floor(p 2^32) for Ising / Potts (Sec. 2, step (1)).
+uint64_t bond_threshold(int model, double beta)
+{
+    const double p = (model == ISING) ? -std::expm1(-2.0 * beta) : -std::expm1(-beta);
+    if (!(p > 0.0)) return 0;
+    return (uint64_t)std::floor(std::ldexp(p, 32));
+}
+
+int validate(int model, int dim, int L, int q, double beta)
+{
+    if (model < 0 || model > 2) return fail(SW_E_INVALID, "model must be 0 (Ising), 1 (Potts) or 2 (XY)");
+    if (dim != 2 && dim != 3) return fail(SW_E_INVALID, "dim must be 2 or 3");
+    if (L < 3) return fail(SW_E_INVALID, "L must be >= 3");
+    double n = 1.0;
+    for (int k = 0; k < dim; ++k) n *= (double)L;
+    if (n > 2147483647.0) return fail(SW_E_INVALID, "L^dim must be < 2^31");
+    if (model == POTTS && (q < 2 || q > 256)) return fail(SW_E_INVALID, "Potts needs 2 <= q <= 256");
+    if (model == ISING && !(q == 0 || q == 2)) return fail(SW_E_INVALID, "Ising takes q = 2 (or 0)");
+    if (!(beta >= 0.0) || !std::isfinite(beta)) return fail(SW_E_INVALID, "beta must be finite and >= 0");
+    return SW_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// One lattice and its device buffers.
+// ---------------------------------------------------------------------------
+struct Lattice {
+    int model = 0, dim = 2, L = 0, q = 2;
+    double beta = 0.0;
+    uint64_t seed = 0;
+    uint32_t rep = 0;
+    int64_t N = 0;
+    int variant = 0;
+    TileShape ts{0, 0, 0};
+    int tiles[3] = {1, 1, 1};
+    int ntiles = 0;
+    int nslots = 0;
+    int64_t sweep = 0;      // index of the next sweep
+    int64_t rec_count = 0;  // records since the last reset
+    int64_t rec_cap = 0;
+    bool measure = true;
+    bool store_bonds = true;
+    bool swept = false;
+    void *state = nullptr;
+    uint32_t *label = nullptr;
+    uint8_t *bond = nullptr;
+    int32_t *face = nullptr;
+    int64_t *part = nullptr;
+    int64_t *rec = nullptr;
+    int64_t face_off[3] = {0, 0, 0};
+    int32_t face_len[3] = {0, 0, 0};
+    InstDesc *d_solo = nullptr;  // descriptor for solo sweeps
+    int2 *d_tmap = nullptr;      // tile map for solo sweeps
+    hipStream_t stream = nullptr;
+
+    ~Lattice() { release(); }
+
+    void release()
+    {
+        void *ptrs[] = {state, label, bond, face, part, rec, d_solo, d_tmap};
+        for (void *p : ptrs)
+            if (p) (void)hipFree(p);
+        state = nullptr;
+        label = nullptr;
+        bond = nullptr;
+        face = nullptr;
+        part = nullptr;
+        rec = nullptr;
+        d_solo = nullptr;
+        d_tmap = nullptr;
+    }
+
+    static int64_t footprint(int model, int dim, int L, int q, int variant)
+    {
+        TileShape s = tile_shape(model, dim, variant);
+        int t[3] = {(L + s.tx - 1) / s.tx, (L + s.ty - 1) / s.ty, dim == 3 ? (L + s.tz - 1) / s.tz : 1};
+        int64_t N = 1;
+        for (int k = 0; k < dim; ++k) N *= L;
+        const int64_t nt = (int64_t)t[0] * t[1] * t[2];
+        const int64_t T = (int64_t)s.tx * s.ty * (dim == 3 ? s.tz : 1);
+        int64_t face = 0;
+        const int ext[3] = {s.tx, s.ty, dim == 3 ? s.tz : 1};
+        for (int mu = 0; mu < dim; ++mu)
+            if (t[mu] > 1) face += nt * 2 * (T / ext[mu]) * 4;
+        const int ns = slots_for(model, q);
+        return N * (int64_t)state_bytes(model) + N * 4 + N + face + nt * ns * 8 + 1025 * ns * 8 +
+               (int64_t)sizeof(InstDesc) + nt * 8;
+    }
+
+    InstDesc desc() const
+    {
+        InstDesc d;
+        std::memset(&d, 0, sizeof(d));
+        d.model = model;
+        d.dim = dim;
+        d.L = L;
+        d.q = q;
+        for (int k = 0; k < 3; ++k) d.tiles[k] = tiles[k];
+        d.ntiles = ntiles;
+        d.nslots = nslots;
+        d.N = N;
+        d.thr = (model == XY) ? 0 : bond_threshold(model, beta);
+        d.two_beta = 2.0 * beta;
+        d.key0 = (uint32_t)(seed & 0xffffffffu);
+        d.key1 = (uint32_t)(seed >> 32);
+        d.rep = rep;
+        d.sweep0 = (uint32_t)sweep;
+        d.count = 0;
+        d.remaining = 0;
+        d.chunk = 1;
+        d.measure = measure ? 1 : 0;
+        d.store_bonds = store_bonds ? 1 : 0;
+        d.rec_row0 = measure ? rec_count : -1;
+        d.rec_cap = rec_cap;
+        d.state = state;
+        d.label = label;
+        d.bond = bond;
+        d.face = face;
+        for (int k = 0; k < 3; ++k) {
+            d.face_off[k] = face_off[k];
+            d.face_len[k] = face_len[k];
+        }
+        d.part = part;
+        d.rec = rec;
+        return d;
+    }
+
+    int grow_records(int64_t need)
+    {
+        if (need <= rec_cap) return SW_OK;
+        int64_t cap = std::max<int64_t>(need, 2 * rec_cap);
+        int64_t *p = nullptr;
+        if (hipMalloc(&p, (size_t)(cap + 1) * nslots * 8) != hipSuccess)
+            return fail(SW_E_NOMEM, "record buffer allocation failed");
+        if (rec && rec_count > 0)
+            HIPCHK(hipMemcpy(p, rec, (size_t)rec_count * nslots * 8, hipMemcpyDeviceToDevice));
+        if (rec) HIPCHK(hipFree(rec));
+        rec = p;
+        rec_cap = cap;
+        return SW_OK;
+    }
+
+    int create(int model_, int dim_, int L_, int q_, double beta_, uint64_t seed_, uint32_t rep_,
+               int variant_, hipStream_t s)
+    {
+        int rc = validate(model_, dim_, L_, q_, beta_);
+        if (rc) return rc;
+        model = model_;
+        dim = dim_;
+        L = L_;
+        q = (model == ISING) ? 2 : (model == XY ? 0 : q_);
+        beta = beta_;
+        seed = seed_;
+        rep = rep_;
+        variant = variant_;
+        stream = s;
+        ts = tile_shape(model, dim, variant);
+        if (ts.tx == 0) return fail(SW_E_INVALID, "unknown tile variant");
+        N = 1;
+        for (int k = 0; k < dim; ++k) N *= L;
+        tiles[0] = (L + ts.tx - 1) / ts.tx;
+        tiles[1] = (L + ts.ty - 1) / ts.ty;
+        tiles[2] = dim == 3 ? (L + ts.tz - 1) / ts.tz : 1;
+        ntiles = tiles[0] * tiles[1] * tiles[2];
+        nslots = slots_for(model, q);
+        const int ext[3] = {ts.tx, ts.ty, dim == 3 ? ts.tz : 1};
+        const int64_t T = (int64_t)ext[0] * ext[1] * ext[2];
+        int64_t face_total = 0;
+        for (int mu = 0; mu < 3; ++mu) {
+            face_len[mu] = (mu < dim) ? (int32_t)(T / ext[mu]) : 0;
+            face_off[mu] = face_total;
+            if (mu < dim && tiles[mu] > 1) face_total += (int64_t)ntiles * 2 * face_len[mu];
+        }
+        if (hipMalloc(&state, (size_t)N * state_bytes(model)) != hipSuccess ||
+            hipMalloc(&label, (size_t)N * 4) != hipSuccess || hipMalloc(&bond, (size_t)N) != hipSuccess ||
+            hipMalloc(&face, (size_t)std::max<int64_t>(face_total, 1) * 4) != hipSuccess ||
+            hipMalloc(&part, (size_t)ntiles * nslots * 8) != hipSuccess ||
+            hipMalloc(&d_solo, sizeof(InstDesc)) != hipSuccess ||
+            hipMalloc(&d_tmap, (size_t)ntiles * sizeof(int2)) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(SW_E_NOMEM, "device allocation failed");
+        }
+        rc = grow_records(1024);
+        if (rc) return rc;
+        std::vector<int2> tm(ntiles);
+        for (int t = 0; t < ntiles; ++t) tm[t] = make_int2(0, t);
+        HIPCHK(hipMemcpy(d_tmap, tm.data(), tm.size() * sizeof(int2), hipMemcpyHostToDevice));
+        HIPCHK(hipMemsetAsync(bond, 0, (size_t)N, stream));
+        // hot start
+        InstDesc d = desc();
+        HIPCHK(hipMemcpyAsync(d_solo, &d, sizeof(d), hipMemcpyHostToDevice, stream));
+        HIPCHK(hipStreamSynchronize(stream));
+        HIPCHK(launch_init(d_solo, 0, d, stream));
+        HIPCHK(hipStreamSynchronize(stream));
+        return SW_OK;
+    }
+
+    // Solo sweeps: one lattice, one launch per kernel per sweep.
+    int sweep_solo(int64_t n)
+    {
+        while (n > 0) {
+            const int64_t m = std::min<int64_t>(n, 1 << 30);
+            if (sweep + m > 0xFFFFFFFFll) return fail(SW_E_INVALID, "sweep index would pass 2^32");
+            if (measure) {
+                int rc = grow_records(rec_count + m);
+                if (rc) return rc;
+            }
+            InstDesc d = desc();
+            d.count = (uint32_t)m;
+            HIPCHK(hipMemcpyAsync(d_solo, &d, sizeof(d), hipMemcpyHostToDevice, stream));
+            HIPCHK(hipStreamSynchronize(stream));
+            for (int64_t k = 0; k < m; ++k) {
+                HIPCHK(launch_bond(model, dim, variant, d_solo, d_tmap, ntiles, (uint32_t)k, 0, stream));
+                HIPCHK(launch_merge(dim, d_solo, d_tmap, ntiles, (uint32_t)k, 0, model, variant, stream));
+                HIPCHK(launch_flip(model, dim, variant, d_solo, d_tmap, ntiles, (uint32_t)k, stream));
+            }
+            HIPCHK(hipStreamSynchronize(stream));
+            sweep += m;
+            if (measure) rec_count += m;
+            swept = true;
+            n -= m;
+        }
+        return SW_OK;
+    }
+
+    // Measure the current configuration alone into the scratch record row.
+    int measure_now(std::vector<int64_t> &row)
+    {
+        InstDesc d = desc();
+        d.count = 1;
+        HIPCHK(hipMemcpyAsync(d_solo, &d, sizeof(d), hipMemcpyHostToDevice, stream));
+        HIPCHK(hipStreamSynchronize(stream));
+        HIPCHK(launch_bond(model, dim, variant, d_solo, d_tmap, ntiles, 0, 1, stream));
+        HIPCHK(launch_merge(dim, d_solo, d_tmap, ntiles, 0, 1, model, variant, stream));
+        row.assign(nslots, 0);
+        HIPCHK(hipMemcpyAsync(row.data(), rec + rec_cap * nslots, (size_t)nslots * 8, hipMemcpyDeviceToHost,
+                              stream));
+        HIPCHK(hipStreamSynchronize(stream));
+        return SW_OK;
+    }
+
+    sw_record to_record(const int64_t *r, int64_t sweep_index) const
+    {
+        sw_record o;
+        std::memset(&o, 0, sizeof(o));
+        o.sweep = sweep_index;
+        const double dN = (double)dim * (double)N;
+        if (model == ISING) {
+            const int64_t al = r[0], M = r[1];
+            o.energy = dN - 2.0 * (double)al;
+            o.mx = (double)M;
+            o.mag = (double)M;
+            o.mag2 = (double)M * (double)M;
+        } else if (model == POTTS) {
+            o.energy = dN - (double)r[0];
+            __int128 s2 = 0;
+            for (int k = 0; k < q; ++k) s2 += (__int128)r[1 + k] * r[1 + k];
+            const __int128 num = (__int128)q * s2 - (__int128)N * N;
+            o.mag2 = (double)num / (double)(q - 1);
+            o.mag = std::sqrt(std::max(0.0, o.mag2));
+        } else {
+            double v[3];
+            std::memcpy(v, r, sizeof(v));
+            o.energy = v[0];
+            o.mx = v[1];
+            o.my = v[2];
+            o.mag2 = v[1] * v[1] + v[2] * v[2];
+            o.mag = std::sqrt(o.mag2);
+        }
+        return o;
+    }
+
+    int series(std::vector<sw_record> &out, int64_t max)
+    {
+        const int64_t n = std::min<int64_t>(rec_count, max);
+        out.clear();
+        if (n <= 0) return SW_OK;
+        std::vector<int64_t> raw((size_t)n * nslots);
+        HIPCHK(hipMemcpy(raw.data(), rec, raw.size() * 8, hipMemcpyDeviceToHost));
+        const int64_t first = sweep - rec_count;
+        for (int64_t i = 0; i < n; ++i) out.push_back(to_record(&raw[(size_t)i * nslots], first + i));
+        return SW_OK;
+    }
+
+    int cluster_stats(sw_cluster_stats *cs)
+    {
+        std::memset(cs, 0, sizeof(*cs));
+        if (!swept) return SW_OK;
+        int32_t *scratch = nullptr;
+        unsigned long long *out = nullptr;
+        if (hipMalloc(&scratch, (size_t)N * 4) != hipSuccess || hipMalloc(&out, 24) != hipSuccess) {
+            if (scratch) (void)hipFree(scratch);
+            return fail(SW_E_NOMEM, "cluster statistics scratch allocation failed");
+        }
+        unsigned long long h[3] = {0, 0, 0};
+        hipError_t e = hipMemcpyAsync(out, h, 24, hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess) e = launch_cluster_stats(d_solo, 0, N, scratch, out, stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(h, out, 24, hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        (void)hipFree(scratch);
+        (void)hipFree(out);
+        if (e != hipSuccess) return fail(SW_E_DEVICE, std::string("cluster statistics: ") + hipGetErrorString(e));
+        cs->n_clusters = (int64_t)h[0];
+        cs->max_cluster = (int64_t)h[1];
+        cs->sum_c2 = (int64_t)h[2];
+        return SW_OK;
+    }
+
+    int averages(double *m2, double *m4, double *energy)
+    {
+        std::vector<sw_record> recs;
+        if (rec_count > 0) {
+            int rc = series(recs, rec_count);
+            if (rc) return rc;
+        } else {
+            std::vector<int64_t> row;
+            int rc = measure_now(row);
+            if (rc) return rc;
+            recs.push_back(to_record(row.data(), sweep));
+        }
+        double a2 = 0, a4 = 0, ae = 0;
+        const double n2 = (double)N * (double)N;
+        for (const sw_record &r : recs) {
+            const double x = r.mag2 / n2;
+            a2 += x;
+            a4 += x * x;
+            ae += r.energy / (double)N;
+        }
+        const double c = (double)recs.size();
+        if (m2) *m2 = a2 / c;
+        if (m4) *m4 = a4 / c;
+        if (energy) *energy = ae / c;
+        return SW_OK;
+    }
+};
+
+struct sw_ctx {
+    Lattice *lat = nullptr;
+    bool owned = false;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+};
+
+static hipStream_t make_stream()
+{
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return nullptr;
+    return s;
+}
+
+// ---------------------------------------------------------------------------
+// Batched form.
+// ---------------------------------------------------------------------------
+struct Group {
+    int model, dim, variant;
+    std::vector<int> members;
+    int ntiles = 0;
+    int2 *d_tmap = nullptr;
+};
+
+struct sw_batch_s {
+    std::vector<std::unique_ptr<Lattice>> lats;
+    std::vector<std::unique_ptr<sw_ctx>> views;
+    std::vector<Group> groups;
+    InstDesc *d_desc = nullptr;
+    InstDesc *h_desc = nullptr;  // pinned
+    hipStream_t stream = nullptr;
+    int chunk = 16;
+    hipGraphExec_t graph = nullptr;
+    int graph_chunk = 0;
+
+    ~sw_batch_s()
+    {
+        if (graph) (void)hipGraphExecDestroy(graph);
+        for (Group &g : groups)
+            if (g.d_tmap) (void)hipFree(g.d_tmap);
+        if (d_desc) (void)hipFree(d_desc);
+        if (h_desc) (void)hipHostFree(h_desc);
+        lats.clear();
+        if (stream) (void)hipStreamDestroy(stream);
+    }
+
+    int build_groups()
+    {
+        std::map<std::tuple<int, int, int>, int> index;
+        for (int j = 0; j < (int)lats.size(); ++j) {
+            const Lattice &l = *lats[j];
+            auto key = std::make_tuple(l.model, l.dim, l.variant);
+            auto it = index.find(key);
+            if (it == index.end()) {
+                index[key] = (int)groups.size();
+                groups.push_back(Group{l.model, l.dim, l.variant, {}, 0, nullptr});
+                it = index.find(key);
+            }
+            groups[it->second].members.push_back(j);
+        }
+        for (Group &g : groups) {
+            std::vector<int2> tm;
+            for (int j : g.members)
+                for (int t = 0; t < lats[j]->ntiles; ++t) tm.push_back(make_int2(j, t));
+            g.ntiles = (int)tm.size();
+            if (hipMalloc(&g.d_tmap, tm.size() * sizeof(int2)) != hipSuccess)
+                return fail(SW_E_NOMEM, "tile map allocation failed");
+            HIPCHK(hipMemcpy(g.d_tmap, tm.data(), tm.size() * sizeof(int2), hipMemcpyHostToDevice));
+        }
+        if (hipMalloc(&d_desc, lats.size() * sizeof(InstDesc)) != hipSuccess ||
+            hipHostMalloc(&h_desc, lats.size() * sizeof(InstDesc), hipHostMallocDefault) != hipSuccess)
+            return fail(SW_E_NOMEM, "descriptor allocation failed");
+        return SW_OK;
+    }
+
+    int enqueue_chunk(int S)
+    {
+        for (int k = 0; k < S; ++k) {
+            for (const Group &g : groups)
+                HIPCHK(launch_bond(g.model, g.dim, g.variant, d_desc, g.d_tmap, g.ntiles, (uint32_t)k, 0, stream));
+            for (const Group &g : groups)
+                HIPCHK(launch_merge(g.dim, d_desc, g.d_tmap, g.ntiles, (uint32_t)k, 0, g.model, g.variant, stream));
+            for (const Group &g : groups)
+                HIPCHK(launch_flip(g.model, g.dim, g.variant, d_desc, g.d_tmap, g.ntiles, (uint32_t)k, stream));
+        }
+        HIPCHK(launch_advance(d_desc, (int)lats.size(), stream));
+        return SW_OK;
+    }
+
+    int capture(int S)
+    {
+        if (graph && graph_chunk == S) return SW_OK;
+        if (graph) {
+            (void)hipGraphExecDestroy(graph);
+            graph = nullptr;
+        }
+        hipGraph_t g = nullptr;
+        HIPCHK(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+        int rc = enqueue_chunk(S);
+        hipError_t e = hipStreamEndCapture(stream, &g);
+        if (rc) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        HIPCHK(e);
+        e = hipGraphInstantiate(&graph, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        HIPCHK(e);
+        graph_chunk = S;
+        return SW_OK;
+    }
+
+    int sweep_counts(const int64_t *counts)
+    {
+        int64_t maxc = 0;
+        for (size_t j = 0; j < lats.size(); ++j) {
+            if (counts[j] < 0) return fail(SW_E_INVALID, "negative sweep count");
+            if (lats[j]->sweep + counts[j] > 0xFFFFFFFFll) return fail(SW_E_INVALID, "sweep index would pass 2^32");
+            if (counts[j] >= (1ll << 31)) return fail(SW_E_INVALID, "sweep count too large");
+            maxc = std::max(maxc, counts[j]);
+        }
+        if (maxc == 0) return SW_OK;
+        const int S = chunk;
+        for (size_t j = 0; j < lats.size(); ++j) {
+            Lattice &l = *lats[j];
+            if (l.measure) {
+                int rc = l.grow_records(l.rec_count + counts[j]);
+                if (rc) return rc;
+            }
+            InstDesc d = l.desc();
+            d.remaining = (uint32_t)counts[j];
+            d.chunk = (uint32_t)S;
+            d.count = (uint32_t)std::min<int64_t>(S, counts[j]);
+            h_desc[j] = d;
+        }
+        HIPCHK(hipMemcpyAsync(d_desc, h_desc, lats.size() * sizeof(InstDesc), hipMemcpyHostToDevice, stream));
+        int rc = capture(S);
+        if (rc) return rc;
+        const int64_t nchunks = (maxc + S - 1) / S;
+        for (int64_t c = 0; c < nchunks; ++c) HIPCHK(hipGraphLaunch(graph, stream));
+        HIPCHK(hipStreamSynchronize(stream));
+        for (size_t j = 0; j < lats.size(); ++j) {
+            Lattice &l = *lats[j];
+            if (counts[j] == 0) continue;
+            l.sweep += counts[j];
+            if (l.measure) l.rec_count += counts[j];
+            l.swept = true;
+        }
+        return SW_OK;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Served form.
+// ---------------------------------------------------------------------------
+struct ServerJob {
+    int64_t id;
+    sw_job job;
+    int64_t footprint;
+    double submit_s = 0, start_s = 0, finish_s = 0;
+    std::unique_ptr<Lattice> lat;
+    int64_t done = 0;
+};
+
+struct sw_server_s {
+    int64_t budget = 0, used = 0;
+    int max_active = 1;
+    int chunk = 32;
+    int64_t next_id = 0;
+    std::deque<std::unique_ptr<ServerJob>> queue;
+    std::vector<std::unique_ptr<ServerJob>> active;
+    std::map<int64_t, sw_job_result> results;
+    std::map<int64_t, std::vector<uint8_t>> final_state;
+    hipStream_t stream = nullptr;
+    // batched launch state for the current active set
+    std::vector<Group> groups;
+    InstDesc *d_desc = nullptr;
+    InstDesc *h_desc = nullptr;
+    int desc_cap = 0;
+    bool dirty = true;
+
+    ~sw_server_s()
+    {
+        for (Group &g : groups)
+            if (g.d_tmap) (void)hipFree(g.d_tmap);
+        if (d_desc) (void)hipFree(d_desc);
+        if (h_desc) (void)hipHostFree(h_desc);
+        active.clear();
+        queue.clear();
+        if (stream) (void)hipStreamDestroy(stream);
+    }
+
+    int rebuild()
+    {
+        for (Group &g : groups)
+            if (g.d_tmap) (void)hipFree(g.d_tmap);
+        groups.clear();
+        if ((int)active.size() > desc_cap) {
+            if (d_desc) (void)hipFree(d_desc);
+            if (h_desc) (void)hipHostFree(h_desc);
+            desc_cap = std::max<int>((int)active.size(), 2 * desc_cap);
+            if (hipMalloc(&d_desc, (size_t)desc_cap * sizeof(InstDesc)) != hipSuccess ||
+                hipHostMalloc(&h_desc, (size_t)desc_cap * sizeof(InstDesc), hipHostMallocDefault) != hipSuccess)
+                return fail(SW_E_NOMEM, "descriptor allocation failed");
+        }
+        std::map<std::tuple<int, int, int>, int> index;
+        for (int j = 0; j < (int)active.size(); ++j) {
+            const Lattice &l = *active[j]->lat;
+            auto key = std::make_tuple(l.model, l.dim, l.variant);
+            if (!index.count(key)) {
+                index[key] = (int)groups.size();
+                groups.push_back(Group{l.model, l.dim, l.variant, {}, 0, nullptr});
+            }
+            groups[index[key]].members.push_back(j);
+        }
+        for (Group &g : groups) {
+            std::vector<int2> tm;
+            for (int j : g.members)
+                for (int t = 0; t < active[j]->lat->ntiles; ++t) tm.push_back(make_int2(j, t));
+            g.ntiles = (int)tm.size();
+            if (hipMalloc(&g.d_tmap, tm.size() * sizeof(int2)) != hipSuccess)
+                return fail(SW_E_NOMEM, "tile map allocation failed");
+            HIPCHK(hipMemcpy(g.d_tmap, tm.data(), tm.size() * sizeof(int2), hipMemcpyHostToDevice));
+        }
+        dirty = false;
+        return SW_OK;
+    }
+
+    int retire(double t)
+    {
+        for (size_t j = 0; j < active.size();) {
+            ServerJob &sj = *active[j];
+            if (sj.done < sj.job.sweeps) {
+                ++j;
+                continue;
+            }
+            sw_job_result r;
+            std::memset(&r, 0, sizeof(r));
+            r.id = sj.id;
+            r.sweeps = sj.done;
+            r.submit_s = sj.submit_s;
+            r.start_s = sj.start_s;
+            r.finish_s = t;
+            int rc = sj.lat->averages(&r.m2, &r.m4, &r.energy);
+            r.status = rc;
+            std::vector<uint8_t> st((size_t)sj.lat->N * state_bytes(sj.lat->model));
+            if (hipMemcpy(st.data(), sj.lat->state, st.size(), hipMemcpyDeviceToHost) != hipSuccess)
+                r.status = SW_E_DEVICE;
+            final_state[sj.id] = std::move(st);
+            results[sj.id] = r;
+            used -= sj.footprint;
+            active.erase(active.begin() + j);
+            dirty = true;
+        }
+        return SW_OK;
+    }
+
+    int admit(double t)
+    {
+        while (!queue.empty() && (int)active.size() < max_active && used + queue.front()->footprint <= budget) {
+            std::unique_ptr<ServerJob> sj = std::move(queue.front());
+            queue.pop_front();
+            sj->lat.reset(new Lattice());
+            const sw_job_desc &jd = sj->job.lattice;
+            int rc = sj->lat->create(jd.model, jd.dim, jd.L, jd.q, jd.beta, jd.seed, jd.replica, 0, stream);
+            if (rc) {
+                sw_job_result r;
+                std::memset(&r, 0, sizeof(r));
+                r.id = sj->id;
+                r.status = rc;
+                r.submit_s = sj->submit_s;
+                r.start_s = r.finish_s = t;
+                results[sj->id] = r;
+                continue;
+            }
+            sj->start_s = t;
+            used += sj->footprint;
+            if (sj->job.sweeps == 0) {
+                sj->lat->swept = false;
+            }
+            active.push_back(std::move(sj));
+            dirty = true;
+        }
+        return SW_OK;
+    }
+
+    int64_t step()
+    {
+        int rc = retire(now_s());
+        if (rc) return rc;
+        rc = admit(now_s());
+        if (rc) return rc;
+        if (!active.empty()) {
+            if (dirty) {
+                rc = rebuild();
+                if (rc) return rc;
+            }
+            int64_t maxc = 0;
+            for (size_t j = 0; j < active.size(); ++j) {
+                Lattice &l = *active[j]->lat;
+                const int64_t c = std::min<int64_t>(chunk, active[j]->job.sweeps - active[j]->done);
+                rc = l.grow_records(l.rec_count + c);
+                if (rc) return rc;
+                InstDesc d = l.desc();
+                d.remaining = (uint32_t)c;
+                d.chunk = (uint32_t)chunk;
+                d.count = (uint32_t)c;
+                h_desc[j] = d;
+                maxc = std::max(maxc, c);
+            }
+            HIPCHK(hipMemcpyAsync(d_desc, h_desc, active.size() * sizeof(InstDesc), hipMemcpyHostToDevice, stream));
+            for (int64_t k = 0; k < maxc; ++k) {
+                for (const Group &g : groups)
+                    HIPCHK(launch_bond(g.model, g.dim, g.variant, d_desc, g.d_tmap, g.ntiles, (uint32_t)k, 0, stream));
+                for (const Group &g : groups)
+                    HIPCHK(launch_merge(g.dim, d_desc, g.d_tmap, g.ntiles, (uint32_t)k, 0, g.model, g.variant, stream));
+                for (const Group &g : groups)
+                    HIPCHK(launch_flip(g.model, g.dim, g.variant, d_desc, g.d_tmap, g.ntiles, (uint32_t)k, stream));
+            }
+            HIPCHK(hipStreamSynchronize(stream));
+            for (size_t j = 0; j < active.size(); ++j) {
+                ServerJob &sj = *active[j];
+                const int64_t c = std::min<int64_t>(chunk, sj.job.sweeps - sj.done);
+                sj.done += c;
+                sj.lat->sweep += c;
+                sj.lat->rec_count += c;
+                if (c > 0) sj.lat->swept = true;
+            }
+            rc = retire(now_s());
+            if (rc) return rc;
+        }
+        return (int64_t)(queue.size() + active.size());
+    }
+};
+
+// ---------------------------------------------------------------------------
+// C ABI.
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char *sw_last_error(void) { return g_err.c_str(); }
+
+sw_handle sw_create_replica(int model, int dim, int L, int q, double beta, uint64_t seed, uint32_t replica)
+{
+    g_err.clear();
+    std::unique_ptr<sw_ctx> h(new sw_ctx());
+    h->stream = make_stream();
+    if (!h->stream) {
+        fail(SW_E_DEVICE, "hipStreamCreate failed (no HIP device?)");
+        return nullptr;
+    }
+    h->own_stream = true;
+    h->lat = new Lattice();
+    h->owned = true;
+    int rc = h->lat->create(model, dim, L, q, beta, seed, replica, 0, h->stream);
+    if (rc) {
+        delete h->lat;
+        (void)hipStreamDestroy(h->stream);
+        h->lat = nullptr;
+        return nullptr;
+    }
+    return h.release();
+}
+
+sw_handle sw_create(int model, int dim, int L, int q, double beta, uint64_t seed)
+{
+    return sw_create_replica(model, dim, L, q, beta, seed, 0);
+}
+
+void sw_destroy(sw_handle h)
+{
+    if (!h) return;
+    if (h->owned) {
+        delete h->lat;
+        if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+        delete h;
+    }
+}
+
+#define CHECK_H(h)                                                   \
+    do {                                                             \
+        if (!(h) || !(h)->lat) return fail(SW_E_INVALID, "NULL handle"); \
+    } while (0)
+
+int sw_sweep(sw_handle h, int64_t n)
+{
+    CHECK_H(h);
+    if (n < 0) return fail(SW_E_INVALID, "negative sweep count");
+    return h->lat->sweep_solo(n);
+}
+
+int sw_measure(sw_handle h, double *m2, double *m4, double *energy, sw_cluster_stats *cs)
+{
+    CHECK_H(h);
+    int rc = h->lat->averages(m2, m4, energy);
+    if (rc) return rc;
+    if (cs) return h->lat->cluster_stats(cs);
+    return SW_OK;
+}
+
+int sw_reset_measure(sw_handle h)
+{
+    CHECK_H(h);
+    h->lat->rec_count = 0;
+    return SW_OK;
+}
+
+int64_t sw_series(sw_handle h, sw_record *out, int64_t max)
+{
+    CHECK_H(h);
+    if (max < 0 || (max > 0 && !out)) return fail(SW_E_INVALID, "bad output buffer");
+    std::vector<sw_record> v;
+    int rc = h->lat->series(v, max);
+    if (rc) return rc;
+    if (!v.empty()) std::memcpy(out, v.data(), v.size() * sizeof(sw_record));
+    return (int64_t)v.size();
+}
+
+int sw_set_measure(sw_handle h, int on)
+{
+    CHECK_H(h);
+    h->lat->measure = on != 0;
+    if (!h->lat->measure) h->lat->rec_count = 0;
+    return SW_OK;
+}
+
+int64_t sw_sweep_index(sw_handle h)
+{
+    CHECK_H(h);
+    return h->lat->sweep;
+}
+
+int sw_set_sweep_index(sw_handle h, int64_t n)
+{
+    CHECK_H(h);
+    if (n < 0 || n > 0xFFFFFFFFll) return fail(SW_E_INVALID, "sweep index out of range");
+    h->lat->sweep = n;
+    h->lat->rec_count = 0;
+    return SW_OK;
+}
+
+int sw_get_state(sw_handle h, void *host)
+{
+    CHECK_H(h);
+    if (!host) return fail(SW_E_INVALID, "NULL buffer");
+    Lattice &l = *h->lat;
+    HIPCHK(hipMemcpy(host, l.state, (size_t)l.N * state_bytes(l.model), hipMemcpyDeviceToHost));
+    return SW_OK;
+}
+
+int sw_set_state(sw_handle h, const void *host)
+{
+    CHECK_H(h);
+    if (!host) return fail(SW_E_INVALID, "NULL buffer");
+    Lattice &l = *h->lat;
+    if (l.model == ISING) {
+        const int8_t *s = (const int8_t *)host;
+        for (int64_t i = 0; i < l.N; ++i)
+            if (s[i] != 1 && s[i] != -1) return fail(SW_E_INVALID, "Ising states must be +1 or -1");
+    } else if (l.model == POTTS) {
+        const uint8_t *s = (const uint8_t *)host;
+        for (int64_t i = 0; i < l.N; ++i)
+            if (s[i] >= l.q) return fail(SW_E_INVALID, "Potts states must be < q");
+    } else {
+        const float *s = (const float *)host;
+        const float top = (float)6.283185307179586476925286766559;
+        for (int64_t i = 0; i < l.N; ++i)
+            if (!(s[i] >= 0.0f && s[i] < top)) return fail(SW_E_INVALID, "XY angles must be in [0, 2pi)");
+    }
+    HIPCHK(hipMemcpy(l.state, host, (size_t)l.N * state_bytes(l.model), hipMemcpyHostToDevice));
+    return SW_OK;
+}
+
+int sw_get_labels(sw_handle h, int32_t *host)
+{
+    CHECK_H(h);
+    if (!host) return fail(SW_E_INVALID, "NULL buffer");
+    Lattice &l = *h->lat;
+    if (!l.swept) {
+        for (int64_t i = 0; i < l.N; ++i) host[i] = (int32_t)i;
+        return SW_OK;
+    }
+    int32_t *tmp = nullptr;
+    if (hipMalloc(&tmp, (size_t)l.N * 4) != hipSuccess) return fail(SW_E_NOMEM, "label scratch allocation failed");
+    InstDesc d = l.desc();
+    hipError_t e = hipMemcpyAsync(l.d_solo, &d, sizeof(d), hipMemcpyHostToDevice, l.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(l.stream);
+    if (e == hipSuccess) e = launch_canon(l.d_solo, 0, l.N, tmp, l.stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(host, tmp, (size_t)l.N * 4, hipMemcpyDeviceToHost, l.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(l.stream);
+    (void)hipFree(tmp);
+    if (e != hipSuccess) return fail(SW_E_DEVICE, std::string("labels: ") + hipGetErrorString(e));
+    return SW_OK;
+}
+
+int sw_get_bonds(sw_handle h, uint8_t *host)
+{
+    CHECK_H(h);
+    if (!host) return fail(SW_E_INVALID, "NULL buffer");
+    Lattice &l = *h->lat;
+    HIPCHK(hipMemcpy(host, l.bond, (size_t)l.N, hipMemcpyDeviceToHost));
+    return SW_OK;
+}
+
+int sw_info(sw_handle h, int *model, int *dim, int *L, int *q, double *beta, uint64_t *seed, uint32_t *replica)
+{
+    CHECK_H(h);
+    const Lattice &l = *h->lat;
+    if (model) *model = l.model;
+    if (dim) *dim = l.dim;
+    if (L) *L = l.L;
+    if (q) *q = l.q;
+    if (beta) *beta = l.beta;
+    if (seed) *seed = l.seed;
+    if (replica) *replica = l.rep;
+    return SW_OK;
+}
+
+sw_batch sw_batch_create(const sw_job_desc *jobs, int n)
+{
+    g_err.clear();
+    if (!jobs || n < 1) {
+        fail(SW_E_INVALID, "need at least one job");
+        return nullptr;
+    }
+    std::unique_ptr<sw_batch_s> b(new sw_batch_s());
+    b->stream = make_stream();
+    if (!b->stream) {
+        fail(SW_E_DEVICE, "hipStreamCreate failed (no HIP device?)");
+        return nullptr;
+    }
+    for (int j = 0; j < n; ++j) {
+        std::unique_ptr<Lattice> l(new Lattice());
+        int rc = l->create(jobs[j].model, jobs[j].dim, jobs[j].L, jobs[j].q, jobs[j].beta, jobs[j].seed,
+                           jobs[j].replica, 0, b->stream);
+        if (rc) return nullptr;
+        std::unique_ptr<sw_ctx> v(new sw_ctx());
+        v->lat = l.get();
+        v->owned = false;
+        v->stream = b->stream;
+        b->views.push_back(std::move(v));
+        b->lats.push_back(std::move(l));
+    }
+    if (b->build_groups()) return nullptr;
+    return b.release();
+}
+
+int sw_batch_sweep(sw_batch b, int64_t n)
+{
+    if (!b) return fail(SW_E_INVALID, "NULL batch");
+    if (n < 0) return fail(SW_E_INVALID, "negative sweep count");
+    std::vector<int64_t> c(b->lats.size(), n);
+    return b->sweep_counts(c.data());
+}
+
+int sw_batch_sweep_counts(sw_batch b, const int64_t *counts)
+{
+    if (!b || !counts) return fail(SW_E_INVALID, "NULL argument");
+    return b->sweep_counts(counts);
+}
+
+int sw_batch_size(sw_batch b) { return b ? (int)b->lats.size() : 0; }
+
+sw_handle sw_batch_member(sw_batch b, int j)
+{
+    if (!b || j < 0 || j >= (int)b->lats.size()) {
+        fail(SW_E_INVALID, "member index out of range");
+        return nullptr;
+    }
+    return b->views[j].get();
+}
+
+int sw_batch_set_chunk(sw_batch b, int s)
+{
+    if (!b || s < 1 || s > 4096) return fail(SW_E_INVALID, "chunk must be in [1, 4096]");
+    b->chunk = s;
+    return SW_OK;
+}
+
+void sw_batch_destroy(sw_batch b) { delete b; }
+
+int64_t sw_footprint(int model, int dim, int L, int q)
+{
+    if (validate(model, dim, L, (model == ISING) ? 2 : q, 0.0)) return SW_E_INVALID;
+    return Lattice::footprint(model, dim, L, (model == ISING) ? 2 : (model == XY ? 0 : q), 0);
+}
+
+sw_server sw_server_create(int64_t budget, int max_active, int chunk)
+{
+    g_err.clear();
+    if (budget <= 0 || max_active < 1 || chunk < 1) {
+        fail(SW_E_INVALID, "budget, max_active and chunk must be positive");
+        return nullptr;
+    }
+    std::unique_ptr<sw_server_s> s(new sw_server_s());
+    s->budget = budget;
+    s->max_active = max_active;
+    s->chunk = chunk;
+    s->stream = make_stream();
+    if (!s->stream) {
+        fail(SW_E_DEVICE, "hipStreamCreate failed (no HIP device?)");
+        return nullptr;
+    }
+    return s.release();
+}
+
+int64_t sw_server_submit(sw_server s, const sw_job *job)
+{
+    if (!s || !job) return fail(SW_E_INVALID, "NULL argument");
+    const sw_job_desc &jd = job->lattice;
+    int rc = validate(jd.model, jd.dim, jd.L, jd.model == ISING ? 2 : jd.q, jd.beta);
+    if (rc) return rc;
+    if (job->sweeps < 0 || job->sweeps >= (1ll << 31)) return fail(SW_E_INVALID, "bad sweep count");
+    const int64_t fp = sw_footprint(jd.model, jd.dim, jd.L, jd.q);
+    if (fp > s->budget) return fail(SW_E_INVALID, "job footprint exceeds the HBM budget");
+    std::unique_ptr<ServerJob> sj(new ServerJob());
+    sj->id = s->next_id++;
+    sj->job = *job;
+    sj->footprint = fp;
+    sj->submit_s = now_s();
+    const int64_t id = sj->id;
+    s->queue.push_back(std::move(sj));
+    return id;
+}
+
+int64_t sw_server_step(sw_server s)
+{
+    if (!s) return fail(SW_E_INVALID, "NULL server");
+    return s->step();
+}
+
+int sw_server_poll(sw_server s, int64_t id, sw_job_result *out, void *state)
+{
+    if (!s) return fail(SW_E_INVALID, "NULL server");
+    auto it = s->results.find(id);
+    if (it == s->results.end()) {
+        if (id >= 0 && id < s->next_id) return 1;
+        return fail(SW_E_NOTFOUND, "unknown job id");
+    }
+    if (out) *out = it->second;
+    if (state) {
+        auto st = s->final_state.find(id);
+        if (st != s->final_state.end()) std::memcpy(state, st->second.data(), st->second.size());
+    }
+    return SW_OK;
+}
+
+void sw_server_destroy(sw_server s) { delete s; }
+
+}  // extern "C"

@@ -1,0 +1,74 @@
+// sw_internal.h -- layout shared by the HIP kernels and the host runtime of
+// libswmc (product code; the oracle does not use it).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace swmc {
+
+enum { ISING = 0, POTTS = 1, XY = 2 };
+enum { TAG_BOND_X = 0, TAG_BOND_Y = 1, TAG_BOND_Z = 2, TAG_CLUSTER = 3, TAG_GLOBAL = 4,
+       TAG_INIT = 5 };
+
+// A label word is either the global index of the site's parent (< 2^31) or,
+// for a cluster root, ROOT_FLAG | the cluster's random decision (Sec. 2,
+// step (3)), so the flip needs no separate per-root array.
+constexpr uint32_t ROOT_FLAG = 0x80000000u;
+
+// Per-lattice descriptor read by every kernel (one per lattice in a batch).
+struct InstDesc {
+    int32_t model, dim, L, q;
+    int32_t tiles[3];     // tiles along x, y, z (z = 1 in 2D)
+    int32_t ntiles;
+    int32_t nslots;       // measurement slots per record
+    int64_t N;
+    uint64_t thr;         // Ising / Potts bond threshold floor(p 2^32)
+    double two_beta;      // XY: 2 beta
+    uint32_t key0, key1, rep;
+    // schedule of the current launch chain: sweep sweep0 + k runs while k < count
+    uint32_t sweep0, count;
+    uint32_t remaining;   // sweeps left in a batched call (advanced on the device)
+    uint32_t chunk;       // sweeps per graph replay
+    int32_t measure;      // write a record per sweep
+    int32_t store_bonds;  // keep the bond bytes in HBM
+    int64_t rec_row0;     // record row of sweep0 (-1: no recording)
+    int64_t rec_cap;      // rows in rec (one extra scratch row follows)
+    void *state;
+    uint32_t *label;
+    uint8_t *bond;
+    int32_t *face;        // per direction mu: [tile][out|in][F_mu]
+    int64_t face_off[3];
+    int32_t face_len[3];
+    int64_t *part;        // [ntiles][nslots] per-tile partial sums
+    int64_t *rec;         // [rec_cap + 1][nslots]
+};
+
+// Tile shape of a kernel variant.
+struct TileShape {
+    int tx, ty, tz;
+};
+
+// Launchers (defined in sw_kernels.hip).  `variant` picks a tile shape from
+// the table tile_shapes(model, dim).
+int num_tile_variants(int model, int dim);
+TileShape tile_shape(int model, int dim, int variant);
+int slots_for(int model, int q);
+
+hipError_t launch_init(const InstDesc *d_desc, int inst, const InstDesc &h, hipStream_t s);
+hipError_t launch_bond(int model, int dim, int variant, const InstDesc *d_desc,
+                       const int2 *d_tmap, int ntiles, uint32_t k, int mode, hipStream_t s);
+hipError_t launch_merge(int dim, const InstDesc *d_desc, const int2 *d_tmap, int ntiles,
+                        uint32_t k, int mode, int variant_model, int variant, hipStream_t s);
+hipError_t launch_flip(int model, int dim, int variant, const InstDesc *d_desc,
+                       const int2 *d_tmap, int ntiles, uint32_t k, hipStream_t s);
+hipError_t launch_canon(const InstDesc *d_desc, int inst, int64_t N, int32_t *d_out,
+                        hipStream_t s);
+hipError_t launch_advance(InstDesc *d_desc, int ninst, hipStream_t s);
+
+}  // namespace swmc
+
+namespace swmc {
+// out3 = {#clusters, max size, sum size^2}; must be zeroed by the caller.
+hipError_t launch_cluster_stats(const InstDesc *d_desc, int inst, int64_t N, int32_t *scratch,
+                                unsigned long long *out3, hipStream_t s);
+}  // namespace swmc

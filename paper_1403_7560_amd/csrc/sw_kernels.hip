@@ -1,0 +1,929 @@
+// sw_kernels.hip -- gfx950 kernels of the Swendsen-Wang sweep.
+//
+// One sweep (Sec. 2 of the paper: (1) active bonds, (2) cluster labelling,
+// (3) random state per cluster) is three launches per (model, dim) group:
+//
+//   k_bond   one workgroup per lattice tile.  Stages the tile and its +1 halo
+//            in LDS, draws the bond words (Philox4x32-10, one block per
+//            4 aligned sites and direction), forms the bonds, measures the
+//            incoming configuration, then labels the tile's clusters with a
+//            union-find in LDS (label equivalence resolved by atomicMin on
+//            roots, fixed point = minimum index).  Local roots receive their
+//            cluster decision; labels and the tile's two faces per direction
+//            go to HBM.
+//   k_merge  global label equivalence across tiles: for every active bond
+//            that crosses a tile face, link the larger root under the smaller
+//            with device-scope atomicMin (Hawick's atomicMin on R[label],
+//            retried until linked, so one pass reaches the fixed point).
+//            An extra grid slice reduces the per-tile measurement partials.
+//   k_flip   every site follows its label chain to the root and takes the
+//            root's decision (Ising +-1, Potts state, XY mirror).
+//
+// Kernels read a per-lattice descriptor and a tile map, so one launch covers
+// any number of lattices of one (model, dim) group (the batched form).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sw_internal.h"
+
+namespace swmc {
+
+#define TWO_PI_D 6.283185307179586476925286766559
+#define PI_D 3.141592653589793238462643383279
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
+// 32x32->64-bit products with the Weyl key schedule.  The key is uniform per
+// launch, so it lives in scalar registers.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint4 philox(uint4 c, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
+        const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+// Component `lane` (0..3) of v with mask arithmetic (a plain ternary chain is
+// lowered to an indexed private-memory load).
+__device__ __forceinline__ uint32_t lane_of(const uint4 &v, uint32_t lane)
+{
+    const uint32_t m1 = 0u - (lane & 1u), m2 = 0u - ((lane >> 1) & 1u);
+    const uint32_t lo = v.x ^ ((v.x ^ v.y) & m1);
+    const uint32_t hi = v.z ^ ((v.z ^ v.w) & m1);
+    return lo ^ ((lo ^ hi) & m2);
+}
+
+__device__ __forceinline__ uint32_t comp(const uint4 &v, int c)
+{
+    return c == 0 ? v.x : (c == 1 ? v.y : (c == 2 ? v.z : v.w));
+}
+
+// The four words of sites gi0 .. gi0+3 from the Philox blocks gi0/4 (a) and
+// gi0/4 + 1 (b).  Aligned quads take the components in place.
+__device__ __forceinline__ void quad_words(uint32_t gi0, const uint4 &a, const uint4 &b, uint32_t w[4])
+{
+    const uint32_t off = gi0 & 3u;
+    if (off == 0) {
+        w[0] = a.x;
+        w[1] = a.y;
+        w[2] = a.z;
+        w[3] = a.w;
+    } else {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const uint32_t p = off + (uint32_t)m;
+            w[m] = (p < 4u) ? lane_of(a, p) : lane_of(b, p - 4u);
+        }
+    }
+}
+
+// Direction of the XY embedding at sweep n: a uniform angle from 53 bits of
+// the GLOBAL stream (words 0 and 1).
+__device__ __forceinline__ double xy_phi(const InstDesc &d, uint32_t n)
+{
+    const uint4 w = philox(make_uint4(0u, n, (uint32_t)TAG_GLOBAL, d.rep), d.key0, d.key1);
+    const double u = ((double)(w.x >> 5) * 67108864.0 + (double)(w.y >> 6)) * 0x1p-53;
+    return TWO_PI_D * u;
+}
+
+// Mirror of an XY spin in the line normal to phi: theta -> pi + 2 phi - theta,
+// wrapped into [0, 2pi) in double, then rounded to float.
+__device__ __forceinline__ float xy_reflect(float th, double phi)
+{
+    double v = (PI_D + 2.0 * phi) - (double)th;
+    if (v >= TWO_PI_D) v -= TWO_PI_D;
+    if (v >= TWO_PI_D) v -= TWO_PI_D;
+    if (v < 0.0) v += TWO_PI_D;
+    float f = (float)v;
+    if (f >= (float)TWO_PI_D) f = 0.0f;
+    return f;
+}
+
+template <int MODEL> struct StateOf;
+template <> struct StateOf<ISING> { typedef int8_t type; };
+template <> struct StateOf<POTTS> { typedef uint8_t type; };
+template <> struct StateOf<XY> { typedef float type; };
+
+__device__ __forceinline__ int wave_sum_i(int v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ double wave_sum_d(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// ---- union-find in LDS (tile-local indices) --------------------------------
+__device__ __forceinline__ int lds_find(volatile int *par, int a)
+{
+    int p = par[a];
+    while (p != a) {
+        a = p;
+        p = par[a];
+    }
+    return a;
+}
+
+__device__ __forceinline__ void lds_union(int *par, int a, int b)
+{
+    volatile int *vp = par;
+    while (true) {
+        a = lds_find(vp, a);
+        b = lds_find(vp, b);
+        if (a == b) return;
+        if (a < b) {
+            const int t = a;
+            a = b;
+            b = t;
+        }
+        const int old = atomicMin(&par[a], b);
+        if (old == a) return;  // a was still a root: now linked under b
+        a = old;               // a was linked meanwhile: merge its parent instead
+    }
+}
+
+// ---- union-find on the global label words -----------------------------------
+__device__ __forceinline__ uint32_t glabel_load(uint32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint32_t gfind(uint32_t *lab, uint32_t a)
+{
+    uint32_t v = glabel_load(lab + a);
+    while (!(v & ROOT_FLAG)) {
+        a = v;
+        v = glabel_load(lab + a);
+    }
+    return a;
+}
+
+__device__ __forceinline__ void gunion(uint32_t *lab, uint32_t a, uint32_t b)
+{
+    while (true) {
+        a = gfind(lab, a);
+        b = gfind(lab, b);
+        if (a == b) return;
+        if (a < b) {
+            const uint32_t t = a;
+            a = b;
+            b = t;
+        }
+        // roots hold ROOT_FLAG|decision > any index, so atomicMin links a root
+        const uint32_t old = atomicMin(lab + a, b);
+        if (old & ROOT_FLAG) return;
+        a = old;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Hot start: word i of the INIT stream (sweep 0) gives the state of site i.
+// One thread per aligned block of four sites.
+// ---------------------------------------------------------------------------
+template <int MODEL>
+__global__ void __launch_bounds__(256) k_init(const InstDesc *__restrict__ descs, int inst)
+{
+    const InstDesc &d = descs[inst];
+    const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (b * 4 >= d.N) return;
+    const uint4 w = philox(make_uint4((uint32_t)b, 0u, (uint32_t)TAG_INIT, d.rep), d.key0, d.key1);
+    const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+    for (int m = 0; m < 4; ++m) {
+        const int64_t i = b * 4 + m;
+        if (i >= d.N) break;
+        if (MODEL == ISING) {
+            ((int8_t *)d.state)[i] = (ws[m] >> 31) ? (int8_t)-1 : (int8_t)1;
+        } else if (MODEL == POTTS) {
+            ((uint8_t *)d.state)[i] = (uint8_t)(((uint64_t)ws[m] * (uint64_t)d.q) >> 32);
+        } else {
+            const double t = ((double)ws[m] * 0x1p-32) * TWO_PI_D;
+            float f = (float)t;
+            if (f >= (float)TWO_PI_D) f = 0.0f;
+            ((float *)d.state)[i] = f;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Bond generation + tile-local labelling + measurement.
+// mode 0: full sweep step; mode 1: measurement of the configuration only.
+// ---------------------------------------------------------------------------
+template <int MODEL, int DIM, int TX, int TY, int TZ>
+__global__ void __launch_bounds__(256) k_bond(const InstDesc *__restrict__ descs,
+                                              const int2 *__restrict__ tmap, uint32_t k, int mode)
+{
+    typedef typename StateOf<MODEL>::type S;
+    constexpr int T = TX * TY * TZ;
+    constexpr int SX = TX + 1, SY = TY + 1, SZ = (DIM == 3) ? TZ + 1 : 1;
+    constexpr int NH = SX * SY * SZ;
+    constexpr int QX = TX / 4;
+    constexpr int NQ = T / 4;
+    constexpr int QPT = (NQ + 255) / 256;
+    constexpr bool IS_XY = (MODEL == XY);
+    static_assert(TX % 4 == 0, "quads along x");
+    static_assert(DIM == 3 || TZ == 1, "2D tiles have TZ = 1");
+
+    __shared__ S s_st[IS_XY ? 1 : NH];
+    __shared__ double2 s_sig[IS_XY ? NH : 1];  // (cos, sin) of theta - phi
+    __shared__ int s_par[T];
+    __shared__ uint8_t s_bond[T];
+    __shared__ int s_hist[MODEL == POTTS ? 256 : 1];
+    __shared__ double s_red[4][3];
+    __shared__ double s_phi;
+
+    const int2 tm = tmap[blockIdx.x];
+    if (tm.x < 0) return;
+    const InstDesc &d = descs[tm.x];
+    if (k >= d.count) return;
+    const uint32_t n = d.sweep0 + k;
+    const int L = d.L;
+    const int t = tm.y;
+    const int tx = t % d.tiles[0];
+    const int ty = (t / d.tiles[0]) % d.tiles[1];
+    const int tz = (DIM == 3) ? t / (d.tiles[0] * d.tiles[1]) : 0;
+    const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
+    const int ex = min(TX, L - x0), ey = min(TY, L - y0), ez = (DIM == 3) ? min(TZ, L - z0) : 1;
+    const int tid = threadIdx.x;
+    const bool full = (mode == 0);
+    const bool meas = (mode == 1) || d.measure;
+
+    if (IS_XY && tid == 0) s_phi = xy_phi(d, n);
+    if (MODEL == POTTS && meas)
+        for (int c = tid; c < d.q; c += 256) s_hist[c] = 0;
+    if (full)
+        for (int l = tid; l < T; l += 256) s_par[l] = l;
+    if (IS_XY) __syncthreads();
+    const double phi = IS_XY ? s_phi : 0.0;
+
+    // ---- stage states (+1 halo in every + direction) ------------------------
+    for (int h = tid; h < NH; h += 256) {
+        const int hx = h % SX, hy = (h / SX) % SY, hz = h / (SX * SY);
+        const int nhalo = (hx == ex) + (hy == ey) + ((DIM == 3) && (hz == ez));
+        if (hx > ex || hy > ey || hz > ((DIM == 3) ? ez : 0) || nhalo > 1) continue;
+        int gx = x0 + hx, gy = y0 + hy, gz = z0 + hz;
+        if (gx >= L) gx -= L;
+        if (gy >= L) gy -= L;
+        if (DIM == 3 && gz >= L) gz -= L;
+        const uint32_t gi = (uint32_t)gx + (uint32_t)L * ((uint32_t)gy + (uint32_t)L * (uint32_t)gz);
+        const S v = ((const S *)d.state)[gi];
+        if (IS_XY) {
+            double sv, cv;
+            sincos((double)v - phi, &sv, &cv);
+            s_sig[h] = make_double2(cv, sv);
+        } else {
+            s_st[h] = v;
+        }
+    }
+    __syncthreads();
+
+    // ---- (1) bonds and measurement -------------------------------------------
+    int cnt_al = 0, cnt_m = 0;
+    double e_acc = 0.0, sx_acc = 0.0, sy_acc = 0.0;
+    uint32_t qb[QPT];
+#pragma unroll
+    for (int j = 0; j < QPT; ++j) {
+        qb[j] = 0;
+        const int qid = tid + 256 * j;
+        if (qid >= NQ) continue;
+        const int qx = qid % QX, row = qid / QX;
+        const int ly = row % TY, lz = row / TY;
+        const int lx0 = qx * 4;
+        if (ly >= ey || lz >= ez || lx0 >= ex) continue;
+        const int nv = min(4, ex - lx0);
+        const uint32_t gi0 = (uint32_t)(x0 + lx0) +
+                             (uint32_t)L * ((uint32_t)(y0 + ly) + (uint32_t)L * (uint32_t)(z0 + lz));
+        uint32_t wq[DIM][4];
+        const bool straddle = ((gi0 & 3u) + (uint32_t)nv) > 4u;
+        if (full) {
+#pragma unroll
+            for (int mu = 0; mu < DIM; ++mu) {
+                const uint4 a = philox(make_uint4(gi0 >> 2, n, (uint32_t)(TAG_BOND_X + mu), d.rep), d.key0, d.key1);
+                uint4 b = a;
+                if (straddle)
+                    b = philox(make_uint4((gi0 >> 2) + 1u, n, (uint32_t)(TAG_BOND_X + mu), d.rep), d.key0, d.key1);
+                quad_words(gi0, a, b, wq[mu]);
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            if (m >= nv) continue;
+            const int lx = lx0 + m;
+            const int h = lx + SX * (ly + SY * lz);
+            uint32_t b = 0;
+#pragma unroll
+            for (int mu = 0; mu < DIM; ++mu) {
+                const int hn = h + (mu == 0 ? 1 : (mu == 1 ? SX : SX * SY));
+                if (IS_XY) {
+                    const double2 a = s_sig[h], c = s_sig[hn];
+                    if (meas) e_acc -= a.x * c.x + a.y * c.y;
+                    if (full) {
+                        const uint32_t wd = wq[mu][m];
+                        const double x = (d.two_beta * a.x) * c.x;
+                        const double p = -expm1(-x);
+                        const double u = (double)wd * 0x1p-32;
+                        if (u < p) b |= 1u << mu;
+                    }
+                } else {
+                    const bool al = s_st[h] == s_st[hn];
+                    cnt_al += al;
+                    if (full) {
+                        const uint32_t wd = wq[mu][m];
+                        if (al && (uint64_t)wd < d.thr) b |= 1u << mu;
+                    }
+                }
+            }
+            if (meas) {
+                if constexpr (MODEL == ISING) cnt_m += s_st[h];
+                else if constexpr (MODEL == POTTS) atomicAdd(&s_hist[s_st[h]], 1);
+                else {
+                    sx_acc += s_sig[h].x;
+                    sy_acc += s_sig[h].y;
+                }
+            }
+            if (full) s_bond[lx + TX * (ly + TY * lz)] = (uint8_t)b;
+            qb[j] |= b << (8 * m);
+        }
+        if (full && d.store_bonds) {
+            if ((gi0 & 3u) == 0 && nv == 4) {
+                *(uint32_t *)(d.bond + gi0) = qb[j];
+            } else {
+                for (int m = 0; m < nv; ++m) d.bond[gi0 + m] = (uint8_t)(qb[j] >> (8 * m));
+            }
+        }
+    }
+
+    // ---- measurement partials of this tile -----------------------------------
+    if (meas) {
+        const int wv = tid >> 6, ln = tid & 63;
+        int64_t *part = d.part + (int64_t)t * d.nslots;
+        if (IS_XY) {
+            const double a = wave_sum_d(e_acc), b = wave_sum_d(sx_acc), c = wave_sum_d(sy_acc);
+            if (ln == 0) {
+                s_red[wv][0] = a;
+                s_red[wv][1] = b;
+                s_red[wv][2] = c;
+            }
+        } else {
+            const int a = wave_sum_i(cnt_al), b = wave_sum_i(cnt_m);
+            if (ln == 0) {
+                s_red[wv][0] = (double)a;
+                s_red[wv][1] = (double)b;
+            }
+        }
+        __syncthreads();
+        if (tid == 0) {
+            if (IS_XY) {
+                for (int c = 0; c < 3; ++c) {
+                    const double v = ((s_red[0][c] + s_red[1][c]) + s_red[2][c]) + s_red[3][c];
+                    part[c] = __double_as_longlong(v);
+                }
+            } else {
+                part[0] = (int64_t)(s_red[0][0] + s_red[1][0] + s_red[2][0] + s_red[3][0]);
+                if (MODEL == ISING)
+                    part[1] = (int64_t)(s_red[0][1] + s_red[1][1] + s_red[2][1] + s_red[3][1]);
+            }
+        }
+        if (MODEL == POTTS)
+            for (int c = tid; c < d.q; c += 256) part[1 + c] = s_hist[c];
+    }
+    if (!full) return;
+    __syncthreads();  // s_par initialised and s_bond complete
+
+    // ---- (2) local labelling: union-find over the tile's internal bonds ------
+#pragma unroll
+    for (int j = 0; j < QPT; ++j) {
+        const int qid = tid + 256 * j;
+        if (qid >= NQ) continue;
+        const int qx = qid % QX, row = qid / QX;
+        const int ly = row % TY, lz = row / TY;
+        const int lx0 = qx * 4;
+        if (ly >= ey || lz >= ez || lx0 >= ex) continue;
+        const int nv = min(4, ex - lx0);
+        for (int m = 0; m < nv; ++m) {
+            const uint32_t b = (qb[j] >> (8 * m)) & 0xffu;
+            if (!b) continue;
+            const int lx = lx0 + m;
+            const int l = lx + TX * (ly + TY * lz);
+            if (b & 1u) {
+                if (lx + 1 < ex) lds_union(s_par, l, l + 1);
+                else if (d.tiles[0] == 1) lds_union(s_par, l, l - lx);
+            }
+            if (b & 2u) {
+                if (ly + 1 < ey) lds_union(s_par, l, l + TX);
+                else if (d.tiles[1] == 1) lds_union(s_par, l, l - TX * ly);
+            }
+            if (DIM == 3 && (b & 4u)) {
+                if (lz + 1 < ez) lds_union(s_par, l, l + TX * TY);
+                else if (d.tiles[2] == 1) lds_union(s_par, l, l - TX * TY * lz);
+            }
+        }
+    }
+    __syncthreads();
+    // compress: every site points straight at its tile-local root
+    for (int l = tid; l < T; l += 256) s_par[l] = lds_find(s_par, l);
+    __syncthreads();
+
+    auto gidx = [&](int r) -> uint32_t {
+        const int rx = r % TX, ry = (r / TX) % TY, rz = r / (TX * TY);
+        return (uint32_t)(x0 + rx) + (uint32_t)L * ((uint32_t)(y0 + ry) + (uint32_t)L * (uint32_t)(z0 + rz));
+    };
+
+    // ---- local roots draw the cluster decision; labels to HBM -----------------
+#pragma unroll
+    for (int j = 0; j < QPT; ++j) {
+        const int qid = tid + 256 * j;
+        if (qid >= NQ) continue;
+        const int qx = qid % QX, row = qid / QX;
+        const int ly = row % TY, lz = row / TY;
+        const int lx0 = qx * 4;
+        if (ly >= ey || lz >= ez || lx0 >= ex) continue;
+        const int nv = min(4, ex - lx0);
+        const uint32_t gi0 = (uint32_t)(x0 + lx0) +
+                             (uint32_t)L * ((uint32_t)(y0 + ly) + (uint32_t)L * (uint32_t)(z0 + lz));
+        const int l0 = lx0 + TX * (ly + TY * lz);
+        bool anyroot = false;
+        for (int m = 0; m < nv; ++m) anyroot |= (s_par[l0 + m] == l0 + m);
+        uint4 c1 = make_uint4(0, 0, 0, 0), c2 = c1;
+        const bool straddle = ((gi0 & 3u) + (uint32_t)nv) > 4u;
+        if (anyroot) {
+            c1 = philox(make_uint4(gi0 >> 2, n, (uint32_t)TAG_CLUSTER, d.rep), d.key0, d.key1);
+            c2 = straddle ? philox(make_uint4((gi0 >> 2) + 1u, n, (uint32_t)TAG_CLUSTER, d.rep), d.key0, d.key1)
+                          : c1;
+        }
+        uint32_t cw[4];
+        quad_words(gi0, c1, c2, cw);
+        uint32_t lab[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            if (m >= nv) continue;
+            const int r = s_par[l0 + m];
+            if (r == l0 + m) {
+                const uint32_t wd = cw[m];
+                const uint32_t dec = (MODEL == POTTS) ? (uint32_t)(((uint64_t)wd * (uint64_t)d.q) >> 32)
+                                                      : (wd >> 31);
+                lab[m] = ROOT_FLAG | dec;
+            } else {
+                lab[m] = gidx(r);
+            }
+        }
+        if ((gi0 & 3u) == 0 && nv == 4) {
+            *(uint4 *)(d.label + gi0) = make_uint4(lab[0], lab[1], lab[2], lab[3]);
+        } else {
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+                if (m < nv) d.label[gi0 + m] = lab[m];
+        }
+    }
+
+    // ---- faces for the global merge --------------------------------------------
+#pragma unroll
+    for (int mu = 0; mu < DIM; ++mu) {
+        if (d.tiles[mu] == 1) continue;
+        const int F = d.face_len[mu];
+        int32_t *fo = d.face + d.face_off[mu] + (int64_t)t * 2 * F;
+        int32_t *fi = fo + F;
+        const int emu = (mu == 0) ? ex : (mu == 1 ? ey : ez);
+        for (int kk = tid; kk < F; kk += 256) {
+            int a, b;  // transverse coordinates
+            bool valid;
+            int lo, li;
+            if (mu == 0) {
+                a = kk % TY;
+                b = kk / TY;
+                valid = a < ey && b < ez;
+                lo = (emu - 1) + TX * (a + TY * b);
+                li = 0 + TX * (a + TY * b);
+            } else if (mu == 1) {
+                a = kk % TX;
+                b = kk / TX;
+                valid = a < ex && b < ez;
+                lo = a + TX * ((emu - 1) + TY * b);
+                li = a + TX * (0 + TY * b);
+            } else {
+                a = kk % TX;
+                b = kk / TX;
+                valid = a < ex && b < ey;
+                lo = a + TX * (b + TY * (emu - 1));
+                li = a + TX * b;
+            }
+            if (!valid) {
+                fo[kk] = -1;
+                fi[kk] = -1;
+                continue;
+            }
+            fo[kk] = ((s_bond[lo] >> mu) & 1u) ? (int32_t)gidx(s_par[lo]) : -1;
+            fi[kk] = (int32_t)gidx(s_par[li]);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Global label equivalence across tile faces + reduction of the measurement.
+// grid = (tiles, DIM + 1); slice mu < DIM merges the +mu face of each tile,
+// slice DIM reduces the per-tile partials into the sweep's record row.
+// ---------------------------------------------------------------------------
+template <int MODEL, int DIM>
+__global__ void __launch_bounds__(256) k_merge(const InstDesc *__restrict__ descs,
+                                               const int2 *__restrict__ tmap, uint32_t k, int mode)
+{
+    __shared__ double s_red[4][3];
+    __shared__ double s_phi;
+    const int2 tm = tmap[blockIdx.x];
+    if (tm.x < 0) return;
+    const InstDesc &d = descs[tm.x];
+    if (k >= d.count) return;
+    const int mu = blockIdx.y;
+    const int t = tm.y;
+    const int tid = threadIdx.x;
+    if (mu < DIM) {
+        if (mode != 0 || d.tiles[mu] == 1) return;
+        int c[3] = {t % d.tiles[0], (t / d.tiles[0]) % d.tiles[1], (DIM == 3) ? t / (d.tiles[0] * d.tiles[1]) : 0};
+        c[mu] = (c[mu] + 1 == d.tiles[mu]) ? 0 : c[mu] + 1;
+        const int nb = c[0] + d.tiles[0] * (c[1] + d.tiles[1] * c[2]);
+        const int F = d.face_len[mu];
+        const int32_t *fo = d.face + d.face_off[mu] + (int64_t)t * 2 * F;
+        const int32_t *fi = d.face + d.face_off[mu] + (int64_t)nb * 2 * F + F;
+        for (int kk = tid; kk < F; kk += 256) {
+            const int32_t a = fo[kk];
+            if (a < 0) continue;
+            gunion(d.label, (uint32_t)a, (uint32_t)fi[kk]);
+        }
+        return;
+    }
+    // reduction slice
+    if (mode == 0 && !d.measure) return;
+    int64_t row;
+    if (mode == 1) {
+        row = d.rec_cap;
+    } else {
+        if (d.rec_row0 < 0) return;
+        row = d.rec_row0 + (int64_t)k;
+        if (row >= d.rec_cap) return;
+    }
+    int64_t *rec = d.rec + row * d.nslots;
+    const int wv = tid >> 6, ln = tid & 63;
+    if (MODEL == XY) {
+        if (t != 0) return;
+        if (tid == 0) s_phi = xy_phi(d, d.sweep0 + k);
+        double acc[3] = {0.0, 0.0, 0.0};
+        for (int tt = tid; tt < d.ntiles; tt += 256)
+            for (int c = 0; c < 3; ++c) acc[c] += __longlong_as_double(d.part[(int64_t)tt * 3 + c]);
+        for (int c = 0; c < 3; ++c) {
+            const double v = wave_sum_d(acc[c]);
+            if (ln == 0) s_red[wv][c] = v;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double v[3];
+            for (int c = 0; c < 3; ++c) v[c] = ((s_red[0][c] + s_red[1][c]) + s_red[2][c]) + s_red[3][c];
+            double sp, cp;
+            sincos(s_phi, &sp, &cp);
+            // sum of (cos, sin)(theta - phi) rotated back by phi
+            const double mx = cp * v[1] - sp * v[2];
+            const double my = sp * v[1] + cp * v[2];
+            rec[0] = __double_as_longlong(v[0]);
+            rec[1] = __double_as_longlong(mx);
+            rec[2] = __double_as_longlong(my);
+        }
+        return;
+    }
+    for (int slot = t; slot < d.nslots; slot += d.ntiles) {
+        long long acc = 0;
+        for (int tt = tid; tt < d.ntiles; tt += 256) acc += d.part[(int64_t)tt * d.nslots + slot];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+        if (ln == 0) s_red[wv][0] = __longlong_as_double(acc);
+        __syncthreads();
+        if (tid == 0) {
+            rec[slot] = __double_as_longlong(s_red[0][0]) + __double_as_longlong(s_red[1][0]) +
+                        __double_as_longlong(s_red[2][0]) + __double_as_longlong(s_red[3][0]);
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// (3) every site takes its cluster root's decision.
+// ---------------------------------------------------------------------------
+template <int MODEL, int DIM, int TX, int TY, int TZ>
+__global__ void __launch_bounds__(256) k_flip(const InstDesc *__restrict__ descs,
+                                              const int2 *__restrict__ tmap, uint32_t k)
+{
+    constexpr int T = TX * TY * TZ;
+    constexpr int QX = TX / 4;
+    constexpr int NQ = T / 4;
+    constexpr int QPT = (NQ + 255) / 256;
+    __shared__ double s_phi;
+    const int2 tm = tmap[blockIdx.x];
+    if (tm.x < 0) return;
+    const InstDesc &d = descs[tm.x];
+    if (k >= d.count) return;
+    const uint32_t n = d.sweep0 + k;
+    const int L = d.L;
+    const int t = tm.y;
+    const int tx = t % d.tiles[0];
+    const int ty = (t / d.tiles[0]) % d.tiles[1];
+    const int tz = (DIM == 3) ? t / (d.tiles[0] * d.tiles[1]) : 0;
+    const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
+    const int ex = min(TX, L - x0), ey = min(TY, L - y0), ez = (DIM == 3) ? min(TZ, L - z0) : 1;
+    const int tid = threadIdx.x;
+    if (MODEL == XY) {
+        if (tid == 0) s_phi = xy_phi(d, n);
+        __syncthreads();
+    }
+    const double phi = (MODEL == XY) ? s_phi : 0.0;
+    const uint32_t *lab = d.label;
+#pragma unroll
+    for (int j = 0; j < QPT; ++j) {
+        const int qid = tid + 256 * j;
+        if (qid >= NQ) continue;
+        const int qx = qid % QX, row = qid / QX;
+        const int ly = row % TY, lz = row / TY;
+        const int lx0 = qx * 4;
+        if (ly >= ey || lz >= ez || lx0 >= ex) continue;
+        const int nv = min(4, ex - lx0);
+        const uint32_t gi0 = (uint32_t)(x0 + lx0) +
+                             (uint32_t)L * ((uint32_t)(y0 + ly) + (uint32_t)L * (uint32_t)(z0 + lz));
+        const bool vec = ((gi0 & 3u) == 0) && nv == 4;
+        uint32_t v[4];
+        if (vec) {
+            const uint4 q4 = *(const uint4 *)(lab + gi0);
+            v[0] = q4.x;
+            v[1] = q4.y;
+            v[2] = q4.z;
+            v[3] = q4.w;
+        } else {
+            for (int m = 0; m < 4; ++m) v[m] = (m < nv) ? lab[gi0 + m] : ROOT_FLAG;
+        }
+        uint32_t dec[4];
+        for (int m = 0; m < 4; ++m) {
+            uint32_t x = v[m];
+            while (!(x & ROOT_FLAG)) x = lab[x];
+            dec[m] = x & 0xffu;
+        }
+        if (MODEL == ISING || MODEL == POTTS) {
+            uint32_t packed = 0;
+            for (int m = 0; m < 4; ++m) {
+                const uint32_t s = (MODEL == ISING) ? (dec[m] ? 0xffu : 0x01u) : dec[m];
+                packed |= s << (8 * m);
+            }
+            if (vec) {
+                *(uint32_t *)((uint8_t *)d.state + gi0) = packed;
+            } else {
+                for (int m = 0; m < nv; ++m) ((uint8_t *)d.state)[gi0 + m] = (uint8_t)(packed >> (8 * m));
+            }
+        } else {
+            float *th = (float *)d.state;
+            if (vec) {
+                float4 a = *(const float4 *)(th + gi0);
+                if (dec[0]) a.x = xy_reflect(a.x, phi);
+                if (dec[1]) a.y = xy_reflect(a.y, phi);
+                if (dec[2]) a.z = xy_reflect(a.z, phi);
+                if (dec[3]) a.w = xy_reflect(a.w, phi);
+                *(float4 *)(th + gi0) = a;
+            } else {
+                for (int m = 0; m < nv; ++m)
+                    if (dec[m]) th[gi0 + m] = xy_reflect(th[gi0 + m], phi);
+            }
+        }
+    }
+}
+
+// Minimum-index labels: follow every chain to its root.
+__global__ void __launch_bounds__(256) k_canon(const InstDesc *__restrict__ descs, int inst,
+                                               int32_t *__restrict__ out)
+{
+    const InstDesc &d = descs[inst];
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= d.N) return;
+    uint32_t r = (uint32_t)i;
+    uint32_t x = d.label[r];
+    while (!(x & ROOT_FLAG)) {
+        r = x;
+        x = d.label[r];
+    }
+    out[i] = (int32_t)r;
+}
+
+// Advance every lattice's schedule by one graph chunk.
+__global__ void k_advance(InstDesc *descs, int ninst)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ninst) return;
+    InstDesc &d = descs[i];
+    const uint32_t used = min(d.chunk, d.remaining);
+    d.sweep0 += used;
+    if (d.rec_row0 >= 0 && d.measure) d.rec_row0 += used;
+    d.remaining -= used;
+    d.count = min(d.chunk, d.remaining);
+}
+
+// ---------------------------------------------------------------------------
+// Variant table and launchers.
+// ---------------------------------------------------------------------------
+#define SW_VARIANTS_ISING2 X(0, 128, 32, 1) X(1, 64, 64, 1) X(2, 256, 16, 1)
+#define SW_VARIANTS_ISING3 X(0, 32, 16, 8) X(1, 16, 16, 16) X(2, 64, 8, 8)
+#define SW_VARIANTS_XY2 X(0, 64, 32, 1) X(1, 32, 32, 1) X(2, 128, 16, 1)
+#define SW_VARIANTS_XY3 X(0, 16, 16, 8) X(1, 32, 8, 8) X(2, 16, 8, 8)
+
+int num_tile_variants(int, int) { return 3; }
+
+TileShape tile_shape(int model, int dim, int v)
+{
+#define X(i, a, b, c) \
+    if (v == i) return TileShape{a, b, c};
+    if (model != XY && dim == 2) { SW_VARIANTS_ISING2 }
+    if (model != XY && dim == 3) { SW_VARIANTS_ISING3 }
+    if (model == XY && dim == 2) { SW_VARIANTS_XY2 }
+    if (model == XY && dim == 3) { SW_VARIANTS_XY3 }
+#undef X
+    return TileShape{0, 0, 0};
+}
+
+int slots_for(int model, int q) { return model == ISING ? 2 : (model == POTTS ? 1 + q : 3); }
+
+hipError_t launch_init(const InstDesc *d_desc, int inst, const InstDesc &h, hipStream_t s)
+{
+    const int64_t blocks4 = (h.N + 3) / 4;
+    const unsigned grid = (unsigned)((blocks4 + 255) / 256);
+    if (h.model == ISING) hipLaunchKernelGGL(k_init<ISING>, dim3(grid), dim3(256), 0, s, d_desc, inst);
+    else if (h.model == POTTS) hipLaunchKernelGGL(k_init<POTTS>, dim3(grid), dim3(256), 0, s, d_desc, inst);
+    else hipLaunchKernelGGL(k_init<XY>, dim3(grid), dim3(256), 0, s, d_desc, inst);
+    return hipGetLastError();
+}
+
+template <int MODEL, int DIM>
+static hipError_t bond_dispatch(int v, const InstDesc *dd, const int2 *tm, int nt, uint32_t k, int mode,
+                                hipStream_t s)
+{
+#define X(i, a, b, c)                                                                                 \
+    if (v == i) {                                                                                     \
+        hipLaunchKernelGGL((k_bond<MODEL, DIM, a, b, c>), dim3(nt), dim3(256), 0, s, dd, tm, k, mode); \
+        return hipGetLastError();                                                                     \
+    }
+    if constexpr (MODEL != XY && DIM == 2) { SW_VARIANTS_ISING2 }
+    if constexpr (MODEL != XY && DIM == 3) { SW_VARIANTS_ISING3 }
+    if constexpr (MODEL == XY && DIM == 2) { SW_VARIANTS_XY2 }
+    if constexpr (MODEL == XY && DIM == 3) { SW_VARIANTS_XY3 }
+#undef X
+    return hipErrorInvalidValue;
+}
+
+template <int MODEL, int DIM>
+static hipError_t flip_dispatch(int v, const InstDesc *dd, const int2 *tm, int nt, uint32_t k, hipStream_t s)
+{
+#define X(i, a, b, c)                                                                         \
+    if (v == i) {                                                                             \
+        hipLaunchKernelGGL((k_flip<MODEL, DIM, a, b, c>), dim3(nt), dim3(256), 0, s, dd, tm, k); \
+        return hipGetLastError();                                                             \
+    }
+    if constexpr (MODEL != XY && DIM == 2) { SW_VARIANTS_ISING2 }
+    if constexpr (MODEL != XY && DIM == 3) { SW_VARIANTS_ISING3 }
+    if constexpr (MODEL == XY && DIM == 2) { SW_VARIANTS_XY2 }
+    if constexpr (MODEL == XY && DIM == 3) { SW_VARIANTS_XY3 }
+#undef X
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_bond(int model, int dim, int v, const InstDesc *dd, const int2 *tm, int nt, uint32_t k,
+                       int mode, hipStream_t s)
+{
+    if (nt <= 0) return hipSuccess;
+    if (model == ISING) return dim == 2 ? bond_dispatch<ISING, 2>(v, dd, tm, nt, k, mode, s)
+                                        : bond_dispatch<ISING, 3>(v, dd, tm, nt, k, mode, s);
+    if (model == POTTS) return dim == 2 ? bond_dispatch<POTTS, 2>(v, dd, tm, nt, k, mode, s)
+                                        : bond_dispatch<POTTS, 3>(v, dd, tm, nt, k, mode, s);
+    return dim == 2 ? bond_dispatch<XY, 2>(v, dd, tm, nt, k, mode, s) : bond_dispatch<XY, 3>(v, dd, tm, nt, k, mode, s);
+}
+
+hipError_t launch_merge(int dim, const InstDesc *dd, const int2 *tm, int nt, uint32_t k, int mode, int model,
+                        int, hipStream_t s)
+{
+    if (nt <= 0) return hipSuccess;
+    const dim3 grid(nt, dim + 1);
+    if (model == ISING) {
+        if (dim == 2) hipLaunchKernelGGL((k_merge<ISING, 2>), grid, dim3(256), 0, s, dd, tm, k, mode);
+        else hipLaunchKernelGGL((k_merge<ISING, 3>), grid, dim3(256), 0, s, dd, tm, k, mode);
+    } else if (model == POTTS) {
+        if (dim == 2) hipLaunchKernelGGL((k_merge<POTTS, 2>), grid, dim3(256), 0, s, dd, tm, k, mode);
+        else hipLaunchKernelGGL((k_merge<POTTS, 3>), grid, dim3(256), 0, s, dd, tm, k, mode);
+    } else {
+        if (dim == 2) hipLaunchKernelGGL((k_merge<XY, 2>), grid, dim3(256), 0, s, dd, tm, k, mode);
+        else hipLaunchKernelGGL((k_merge<XY, 3>), grid, dim3(256), 0, s, dd, tm, k, mode);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_flip(int model, int dim, int v, const InstDesc *dd, const int2 *tm, int nt, uint32_t k,
+                       hipStream_t s)
+{
+    if (nt <= 0) return hipSuccess;
+    if (model == ISING) return dim == 2 ? flip_dispatch<ISING, 2>(v, dd, tm, nt, k, s)
+                                        : flip_dispatch<ISING, 3>(v, dd, tm, nt, k, s);
+    if (model == POTTS) return dim == 2 ? flip_dispatch<POTTS, 2>(v, dd, tm, nt, k, s)
+                                        : flip_dispatch<POTTS, 3>(v, dd, tm, nt, k, s);
+    return dim == 2 ? flip_dispatch<XY, 2>(v, dd, tm, nt, k, s) : flip_dispatch<XY, 3>(v, dd, tm, nt, k, s);
+}
+
+hipError_t launch_canon(const InstDesc *dd, int inst, int64_t N, int32_t *out, hipStream_t s)
+{
+    const unsigned grid = (unsigned)((N + 255) / 256);
+    hipLaunchKernelGGL(k_canon, dim3(grid), dim3(256), 0, s, dd, inst, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_advance(InstDesc *dd, int ninst, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_advance, dim3((ninst + 255) / 256), dim3(256), 0, s, dd, ninst);
+    return hipGetLastError();
+}
+
+}  // namespace swmc
+
+namespace swmc {
+
+// ---------------------------------------------------------------------------
+// Cluster statistics of the last labelling (diagnostic path of sw_measure).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_fill_i32(int32_t *p, int64_t n, int32_t v)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void __launch_bounds__(256) k_csize(const InstDesc *__restrict__ descs, int inst,
+                                               int32_t *__restrict__ size)
+{
+    const InstDesc &d = descs[inst];
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= d.N) return;
+    uint32_t r = (uint32_t)i;
+    uint32_t x = d.label[r];
+    while (!(x & ROOT_FLAG)) {
+        r = x;
+        x = d.label[r];
+    }
+    atomicAdd(size + r, 1);
+}
+
+__global__ void __launch_bounds__(256) k_cstats(const int32_t *__restrict__ size, int64_t n,
+                                                unsigned long long *out)
+{
+    __shared__ long long s_c[4], s_m[4], s_q[4];
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    long long c = 0, m = 0, q = 0;
+    if (i < n) {
+        const long long v = size[i];
+        c = v > 0;
+        m = v;
+        q = v * v;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        c += __shfl_xor(c, off, 64);
+        q += __shfl_xor(q, off, 64);
+        const long long o = __shfl_xor(m, off, 64);
+        m = o > m ? o : m;
+    }
+    const int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        s_c[wv] = c;
+        s_m[wv] = m;
+        s_q[wv] = q;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        long long cc = 0, mm = 0, qq = 0;
+        for (int w = 0; w < 4; ++w) {
+            cc += s_c[w];
+            qq += s_q[w];
+            mm = s_m[w] > mm ? s_m[w] : mm;
+        }
+        atomicAdd(out + 0, (unsigned long long)cc);
+        atomicMax(out + 1, (unsigned long long)mm);
+        atomicAdd(out + 2, (unsigned long long)qq);
+    }
+}
+
+hipError_t launch_cluster_stats(const InstDesc *dd, int inst, int64_t N, int32_t *scratch,
+                                unsigned long long *out3, hipStream_t s)
+{
+    const unsigned grid = (unsigned)((N + 255) / 256);
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid), dim3(256), 0, s, scratch, N, 0);
+    hipLaunchKernelGGL(k_csize, dim3(grid), dim3(256), 0, s, dd, inst, scratch);
+    hipLaunchKernelGGL(k_cstats, dim3(grid), dim3(256), 0, s, (const int32_t *)scratch, N, out3);
+    return hipGetLastError();
+}
+
+}  // namespace swmc

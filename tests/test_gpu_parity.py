@@ -1,0 +1,184 @@
+"""GPU parity: the HIP path (through the C ABI) against the oracle.
+
+Ising and Potts: states, labels and bonds must match bit for bit after N
+sweeps, and the per-sweep records exactly.  XY: bonds must match exactly and
+angles within 1e-5 rad (circular distance); the FP64 bond test and the mirror
+are evaluated in the same order on both sides, so they are expected to agree
+bit for bit as well.
+
+Sizes span several tiles with a ragged tail (tiles are 128x32 / 64x32 in 2D
+and 32x16x8 / 16x16x8 in 3D) plus lattices smaller than one tile, where the
+periodic wrap stays inside the tile.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1403_7560_amd import inputs
+
+sw = pytest.importorskip("paper_1403_7560_amd")
+pytestmark = pytest.mark.gpu
+
+ISING, POTTS, XY = oracle.ISING, oracle.POTTS, oracle.XY
+TWO_PI_F = np.float32(2 * math.pi)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def circ(a, b):
+    d = np.abs(a.astype(np.float64) - b.astype(np.float64))
+    return np.minimum(d, 2 * math.pi - d)
+
+
+def compare_lattice(model, got_state, got_labels, got_bonds, ref):
+    np.testing.assert_array_equal(got_bonds, ref["bonds"], err_msg="bonds differ")
+    if model == XY:
+        assert circ(got_state, ref["state"]).max(initial=0.0) < 1e-5
+    else:
+        np.testing.assert_array_equal(got_state, ref["state"], err_msg="states differ")
+    np.testing.assert_array_equal(got_labels, ref["labels"], err_msg="labels differ")
+
+
+def compare_records(model, dim, L, q, series, rec):
+    N = L ** dim
+    if model == ISING:
+        np.testing.assert_array_equal(series["energy"], rec["energy"])
+        np.testing.assert_array_equal(series["mx"], rec["mx"])
+    elif model == POTTS:
+        np.testing.assert_array_equal(series["energy"], rec["energy"])
+        np.testing.assert_allclose(series["mag2"], rec["mx"], rtol=1e-12, atol=1e-6)
+    else:
+        np.testing.assert_allclose(series["energy"], rec["energy"], rtol=1e-9, atol=1e-9 * dim * N)
+        np.testing.assert_allclose(series["mx"], rec["mx"], rtol=1e-9, atol=1e-9 * N)
+        np.testing.assert_allclose(series["my"], rec["my"], rtol=1e-9, atol=1e-9 * N)
+
+
+CASES = [
+    # model, dim, L, q, T, sweeps
+    (ISING, 2, 3, 2, 2.269185, 20),
+    (ISING, 2, 64, 2, 2.269185, 30),
+    (ISING, 2, 130, 2, 2.0, 8),
+    (ISING, 2, 257, 2, 2.5, 4),
+    (POTTS, 2, 5, 3, 0.994972861, 20),
+    (POTTS, 2, 130, 3, 0.994972861, 6),
+    (POTTS, 2, 67, 10, 0.701231568, 6),
+    (POTTS, 2, 40, 256, 0.3, 4),
+    (ISING, 3, 3, 2, 4.5115, 20),
+    (ISING, 3, 33, 2, 4.5115, 5),
+    (ISING, 3, 40, 2, 4.0, 4),
+    (POTTS, 3, 17, 3, 1.8, 5),
+    (POTTS, 3, 34, 4, 1.6, 3),
+    (XY, 2, 5, 0, 0.89, 15),
+    (XY, 2, 70, 0, 0.89, 5),
+    (XY, 2, 131, 0, 1.2, 3),
+    (XY, 3, 3, 0, 2.2019, 15),
+    (XY, 3, 18, 0, 2.2019, 4),
+    (XY, 3, 33, 0, 2.0, 3),
+]
+
+
+@pytest.mark.parametrize("model,dim,L,q,T,n", CASES)
+def test_hot_start_and_sweeps(model, dim, L, q, T, n):
+    say(f"[parity] model={model} dim={dim} L={L} q={q} T={T} sweeps={n}")
+    seed = 1000 + 17 * L + model
+    beta = 1.0 / T
+    lat = sw.Lattice(model, dim, L, q, beta, seed)
+    s0 = oracle.init_state(model, dim, L, q, seed)
+    got0 = lat.get_state()
+    if model == XY:
+        np.testing.assert_array_equal(got0.view(np.uint32), s0.view(np.uint32))
+    else:
+        np.testing.assert_array_equal(got0, s0)
+    lat.sweep(n)
+    ref = oracle.sweeps(model, dim, L, q, beta, seed, 0, 0, n, s0)
+    compare_lattice(model, lat.get_state(), lat.get_labels(), lat.get_bonds(), ref)
+    compare_records(model, dim, L, q, lat.series(), ref["records"])
+    assert lat.sweep_index() == n
+    lat.close()
+
+
+@pytest.mark.parametrize("model,dim,L,q,T", [(ISING, 2, 100, 2, 2.3), (POTTS, 3, 20, 5, 1.0),
+                                             (XY, 2, 66, 0, 1.1), (XY, 3, 20, 0, 2.2)])
+def test_window_from_generated_state(model, dim, L, q, T):
+    """Resume at a later stream position from a seeded synthetic state."""
+    say(f"[window] model={model} dim={dim} L={L} q={q}")
+    seed, n0, n = 77, 123456, 3
+    beta = 1.0 / T
+    st = inputs.random_state(model, dim, L, q, seed=5)
+    lat = sw.Lattice(model, dim, L, q, beta, seed, replica=3)
+    lat.set_state(st)
+    lat.set_sweep_index(n0)
+    lat.sweep(n)
+    ref = oracle.sweeps(model, dim, L, q, beta, seed, 3, n0, n, st)
+    compare_lattice(model, lat.get_state(), lat.get_labels(), lat.get_bonds(), ref)
+    compare_records(model, dim, L, q, lat.series(), ref["records"])
+    lat.close()
+
+
+def test_sweeps_split_across_calls():
+    say("[split] Ising 2D L=80 in 3 calls")
+    lat = sw.Lattice(ISING, 2, 80, 2, 0.44, 9)
+    for n in (3, 0, 5, 1):
+        lat.sweep(n)
+    ref = oracle.sweeps(ISING, 2, 80, 2, 0.44, 9, 0, 0, 9, oracle.init_state(ISING, 2, 80, 2, 9))
+    compare_lattice(ISING, lat.get_state(), lat.get_labels(), lat.get_bonds(), ref)
+    compare_records(ISING, 2, 80, 2, lat.series(), ref["records"])
+
+
+@pytest.mark.parametrize("beta", [0.0, 50.0])
+def test_degenerate_couplings(beta):
+    """beta = 0: no bond is active, every site is its own cluster.
+    beta -> infinity: every aligned bond is active (p = 1)."""
+    say(f"[degenerate] beta={beta}")
+    for model, dim, L, q in [(ISING, 2, 37, 2), (POTTS, 3, 9, 3), (XY, 2, 19, 0)]:
+        lat = sw.Lattice(model, dim, L, q, beta, 4)
+        s0 = lat.get_state()
+        lat.sweep(2)
+        ref = oracle.sweeps(model, dim, L, q, beta, 4, 0, 0, 2, s0)
+        compare_lattice(model, lat.get_state(), lat.get_labels(), lat.get_bonds(), ref)
+        if beta == 0.0:
+            assert np.array_equal(lat.get_labels(), np.arange(L ** dim, dtype=np.int32))
+
+
+def test_measure_and_cluster_stats():
+    say("[measure] Ising 2D L=64 and Potts 3D")
+    for model, dim, L, q, beta in [(ISING, 2, 64, 2, 1 / 2.269185), (POTTS, 3, 12, 3, 0.5)]:
+        seed = 31
+        lat = sw.Lattice(model, dim, L, q, beta, seed)
+        s0 = lat.get_state()
+        lat.sweep(10)
+        lat.reset_measure()
+        lat.sweep(25)
+        got = lat.measure()
+        ref = oracle.sweeps(model, dim, L, q, beta, seed, 0, 0, 35, s0)
+        N = L ** dim
+        mx = ref["records"]["mx"][10:]
+        m2 = (mx / N) ** 2 if model == ISING else mx / N ** 2
+        assert got["m2"] == pytest.approx(m2.mean(), rel=1e-12)
+        assert got["m4"] == pytest.approx((m2 ** 2).mean(), rel=1e-12)
+        assert got["energy"] == pytest.approx(ref["records"]["energy"][10:].mean() / N, rel=1e-12)
+        cs = oracle.cluster_stats(ref["labels"])
+        assert (got["n_clusters"], got["max_cluster"], got["sum_c2"]) == (
+            cs["n_clusters"], cs["max_cluster"], cs["sum_c2"])
+
+
+def test_invalid_arguments():
+    say("[invalid]")
+    for args in [(3, 2, 10, 2), (ISING, 4, 10, 2), (ISING, 2, 2, 2), (POTTS, 2, 10, 1),
+                 (POTTS, 2, 10, 257), (ISING, 3, 1291, 2)]:
+        with pytest.raises(sw.SWError):
+            sw.Lattice(*args, beta=0.4, seed=1)
+    with pytest.raises(sw.SWError):
+        sw.Lattice(ISING, 2, 10, 2, beta=-1.0)
+    lat = sw.Lattice(POTTS, 2, 10, 3, 0.5, 1)
+    bad = np.full(100, 3, dtype=np.uint8)
+    with pytest.raises(sw.SWError):
+        lat.set_state(bad)
+    with pytest.raises(sw.SWError):
+        lat.sweep(-1)
