@@ -112,6 +112,14 @@ void sw_destroy(sw_handle h);
 /* Message of the last error on the calling thread ("" if none). */
 const char *sw_last_error(void);
 
+/* Per-kernel device time.  While on, every launch of the three sweep
+ * kernels (0 = bond generation + tile labelling, 1 = label merge across
+ * tiles, 2 = cluster flip) is bracketed by HIP events on the handle's stream
+ * and its duration accumulated.  sw_profile(h, 1) also clears the totals. */
+int sw_profile(sw_handle h, int on);
+/* Accumulated milliseconds and launch counts per kernel (3 entries each). */
+int sw_profile_read(sw_handle h, double *ms, int64_t *launches);
+
 /* --- state access (checkpoint / parity hooks) ----------------------------- */
 
 /* Number of sweeps done so far (the next sweep's index n). */

@@ -64,6 +64,8 @@ SIGNATURES = {
     "sw_set_measure": (i32, [vp, i32]),
     "sw_destroy": (None, [vp]),
     "sw_last_error": (ctypes.c_char_p, []),
+    "sw_profile": (i32, [vp, i32]),
+    "sw_profile_read": (i32, [vp, vp, vp]),
     "sw_sweep_index": (i64, [vp]),
     "sw_set_sweep_index": (i32, [vp, i64]),
     "sw_get_state": (i32, [vp, vp]),
@@ -176,6 +178,15 @@ class Lattice:
         out = {k: np.array([getattr(buf[i], k) for i in range(got)])
                for k in ("sweep", "energy", "mag", "mag2", "mx", "my")}
         return out
+
+    def profile(self, on):
+        _check(lib().sw_profile(self.h, 1 if on else 0))
+
+    def profile_read(self):
+        ms = np.zeros(3)
+        n = np.zeros(3, dtype=np.int64)
+        _check(lib().sw_profile_read(self.h, _ptr(ms), _ptr(n)))
+        return {"bond": (ms[0], n[0]), "merge": (ms[1], n[1]), "flip": (ms[2], n[2])}
 
     def sweep_index(self):
         return _check(lib().sw_sweep_index(self.h))

@@ -102,8 +102,27 @@ struct Lattice {
     InstDesc *d_solo = nullptr;  // descriptor for solo sweeps
     int2 *d_tmap = nullptr;      // tile map for solo sweeps
     hipStream_t stream = nullptr;
+    // per-kernel event timing
+    bool profiling = false;
+    std::vector<hipEvent_t> events;
+    double prof_ms[3] = {0, 0, 0};
+    int64_t prof_n[3] = {0, 0, 0};
 
-    ~Lattice() { release(); }
+    ~Lattice()
+    {
+        for (hipEvent_t e : events) (void)hipEventDestroy(e);
+        release();
+    }
+
+    int ensure_events(size_t n)
+    {
+        while (events.size() < n) {
+            hipEvent_t e;
+            HIPCHK(hipEventCreate(&e));
+            events.push_back(e);
+        }
+        return SW_OK;
+    }
 
     void release()
     {
@@ -259,12 +278,31 @@ struct Lattice {
             d.count = (uint32_t)m;
             HIPCHK(hipMemcpyAsync(d_solo, &d, sizeof(d), hipMemcpyHostToDevice, stream));
             HIPCHK(hipStreamSynchronize(stream));
+            if (profiling) {
+                int rc = ensure_events((size_t)(4 * m));
+                if (rc) return rc;
+            }
             for (int64_t k = 0; k < m; ++k) {
+                hipEvent_t *ev = profiling ? &events[(size_t)(4 * k)] : nullptr;
+                if (ev) HIPCHK(hipEventRecord(ev[0], stream));
                 HIPCHK(launch_bond(model, dim, variant, d_solo, d_tmap, ntiles, (uint32_t)k, 0, stream));
+                if (ev) HIPCHK(hipEventRecord(ev[1], stream));
                 HIPCHK(launch_merge(dim, d_solo, d_tmap, ntiles, (uint32_t)k, 0, model, variant, stream));
+                if (ev) HIPCHK(hipEventRecord(ev[2], stream));
                 HIPCHK(launch_flip(model, dim, variant, d_solo, d_tmap, ntiles, (uint32_t)k, stream));
+                if (ev) HIPCHK(hipEventRecord(ev[3], stream));
             }
             HIPCHK(hipStreamSynchronize(stream));
+            if (profiling) {
+                for (int64_t k = 0; k < m; ++k) {
+                    for (int c = 0; c < 3; ++c) {
+                        float ms = 0.f;
+                        HIPCHK(hipEventElapsedTime(&ms, events[(size_t)(4 * k + c)], events[(size_t)(4 * k + c + 1)]));
+                        prof_ms[c] += ms;
+                        prof_n[c] += 1;
+                    }
+                }
+            }
             sweep += m;
             if (measure) rec_count += m;
             swept = true;
@@ -807,6 +845,28 @@ int sw_set_measure(sw_handle h, int on)
     CHECK_H(h);
     h->lat->measure = on != 0;
     if (!h->lat->measure) h->lat->rec_count = 0;
+    return SW_OK;
+}
+
+int sw_profile(sw_handle h, int on)
+{
+    CHECK_H(h);
+    h->lat->profiling = on != 0;
+    if (on)
+        for (int c = 0; c < 3; ++c) {
+            h->lat->prof_ms[c] = 0.0;
+            h->lat->prof_n[c] = 0;
+        }
+    return SW_OK;
+}
+
+int sw_profile_read(sw_handle h, double *ms, int64_t *launches)
+{
+    CHECK_H(h);
+    for (int c = 0; c < 3; ++c) {
+        if (ms) ms[c] = h->lat->prof_ms[c];
+        if (launches) launches[c] = h->lat->prof_n[c];
+    }
     return SW_OK;
 }
 

@@ -125,14 +125,19 @@ __device__ __forceinline__ double wave_sum_d(double v)
 }
 
 // ---- union-find in LDS (tile-local indices) --------------------------------
+// Root of a with path halving: a non-root's parent may be replaced by any
+// ancestor (every pointer goes to a smaller index of the same cluster), so
+// the plain store is safe against concurrent unions.
 __device__ __forceinline__ int lds_find(volatile int *par, int a)
 {
-    int p = par[a];
-    while (p != a) {
-        a = p;
-        p = par[a];
+    while (true) {
+        const int p = par[a];
+        if (p == a) return a;
+        const int g = par[p];
+        if (g == p) return p;
+        par[a] = g;
+        a = g;
     }
-    return a;
 }
 
 __device__ __forceinline__ void lds_union(int *par, int a, int b)
@@ -159,14 +164,22 @@ __device__ __forceinline__ uint32_t glabel_load(uint32_t *p)
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+__device__ __forceinline__ void glabel_store(uint32_t *p, uint32_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Root of a on the global label words, with path halving (see lds_find).
 __device__ __forceinline__ uint32_t gfind(uint32_t *lab, uint32_t a)
 {
-    uint32_t v = glabel_load(lab + a);
-    while (!(v & ROOT_FLAG)) {
-        a = v;
-        v = glabel_load(lab + a);
+    while (true) {
+        const uint32_t p = glabel_load(lab + a);
+        if (p & ROOT_FLAG) return a;
+        const uint32_t g = glabel_load(lab + p);
+        if (g & ROOT_FLAG) return p;
+        glabel_store(lab + a, g);
+        a = g;
     }
-    return a;
 }
 
 __device__ __forceinline__ void gunion(uint32_t *lab, uint32_t a, uint32_t b)
@@ -225,18 +238,23 @@ __global__ void __launch_bounds__(256) k_bond(const InstDesc *__restrict__ descs
 {
     typedef typename StateOf<MODEL>::type S;
     constexpr int T = TX * TY * TZ;
-    constexpr int SX = TX + 1, SY = TY + 1, SZ = (DIM == 3) ? TZ + 1 : 1;
+    constexpr int SX = TX + 4, SY = TY + 1, SZ = (DIM == 3) ? TZ + 1 : 1;  // rows padded to 4 bytes
     constexpr int NH = SX * SY * SZ;
     constexpr int QX = TX / 4;
     constexpr int NQ = T / 4;
     constexpr int QPT = (NQ + 255) / 256;
     constexpr bool IS_XY = (MODEL == XY);
     static_assert(TX % 4 == 0, "quads along x");
+    static_assert(TX == 64, "a tile row is one wavefront (lane = column) in the labelling scan");
+    static_assert(T <= 32768, "provisional labels are 16-bit");
+    static_assert((TY * TZ) % 4 == 0, "whole rows per wavefront");
+    static_assert(NQ % 256 == 0, "whole quads per thread");
     static_assert(DIM == 3 || TZ == 1, "2D tiles have TZ = 1");
 
-    __shared__ S s_st[IS_XY ? 1 : NH];
+    __shared__ __align__(16) S s_st[IS_XY ? 4 : NH];
     __shared__ double2 s_sig[IS_XY ? NH : 1];  // (cos, sin) of theta - phi
-    __shared__ int s_par[T];
+    __shared__ int s_par[T];         // equivalence table over provisional labels
+    __shared__ int16_t s_plab[T];    // provisional label of every site
     __shared__ uint8_t s_bond[T];
     __shared__ int s_hist[MODEL == POTTS ? 256 : 1];
     __shared__ double s_red[4][3];
@@ -267,22 +285,112 @@ __global__ void __launch_bounds__(256) k_bond(const InstDesc *__restrict__ descs
     const double phi = IS_XY ? s_phi : 0.0;
 
     // ---- stage states (+1 halo in every + direction) ------------------------
-    for (int h = tid; h < NH; h += 256) {
-        const int hx = h % SX, hy = (h / SX) % SY, hz = h / (SX * SY);
-        const int nhalo = (hx == ex) + (hy == ey) + ((DIM == 3) && (hz == ez));
-        if (hx > ex || hy > ey || hz > ((DIM == 3) ? ez : 0) || nhalo > 1) continue;
-        int gx = x0 + hx, gy = y0 + hy, gz = z0 + hz;
-        if (gx >= L) gx -= L;
-        if (gy >= L) gy -= L;
-        if (DIM == 3 && gz >= L) gz -= L;
-        const uint32_t gi = (uint32_t)gx + (uint32_t)L * ((uint32_t)gy + (uint32_t)L * (uint32_t)gz);
-        const S v = ((const S *)d.state)[gi];
-        if (IS_XY) {
-            double sv, cv;
-            sincos((double)v - phi, &sv, &cv);
-            s_sig[h] = make_double2(cv, sv);
-        } else {
-            s_st[h] = v;
+    // Interior: one 4-site load per quad, all issued before any LDS store.
+    {
+        uint32_t raw[QPT];      // Ising / Potts: four states
+        float4 rawf[QPT];       // XY: four angles
+#pragma unroll
+        for (int j = 0; j < QPT; ++j) {
+            const int qid = tid + 256 * j;
+            const int qx = qid % QX, row = qid / QX;
+            const int ly = row % TY, lz = row / TY;
+            const int lx0 = qx * 4;
+            raw[j] = 0;
+            rawf[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (ly >= ey || lz >= ez || lx0 >= ex) continue;
+            const int nv = min(4, ex - lx0);
+            const uint32_t gi0 = (uint32_t)(x0 + lx0) +
+                                 (uint32_t)L * ((uint32_t)(y0 + ly) + (uint32_t)L * (uint32_t)(z0 + lz));
+            if ((gi0 & 3u) == 0 && nv == 4) {
+                if (IS_XY) rawf[j] = *(const float4 *)((const float *)d.state + gi0);
+                else raw[j] = *(const uint32_t *)((const uint8_t *)d.state + gi0);
+            } else if (IS_XY) {
+                const float *st = (const float *)d.state + gi0;
+                rawf[j].x = st[0];
+                if (nv > 1) rawf[j].y = st[1];
+                if (nv > 2) rawf[j].z = st[2];
+                if (nv > 3) rawf[j].w = st[3];
+            } else {
+                const uint8_t *st = (const uint8_t *)d.state + gi0;
+                for (int m = 0; m < nv; ++m) raw[j] |= (uint32_t)st[m] << (8 * m);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < QPT; ++j) {
+            const int qid = tid + 256 * j;
+            const int qx = qid % QX, row = qid / QX;
+            const int ly = row % TY, lz = row / TY;
+            const int lx0 = qx * 4;
+            if (ly >= ey || lz >= ez || lx0 >= ex) continue;
+            const int nv = min(4, ex - lx0);
+            const int h = lx0 + SX * (ly + SY * lz);
+            // a partial quad stores only its own sites: the cell after it may be
+            // the +x halo, written by another thread
+            if (IS_XY) {
+                const float a[4] = {rawf[j].x, rawf[j].y, rawf[j].z, rawf[j].w};
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    if (m >= nv) continue;
+                    double sv, cv;
+                    sincos((double)a[m] - phi, &sv, &cv);
+                    s_sig[h + m] = make_double2(cv, sv);
+                }
+            } else if (nv == 4) {
+                *(uint32_t *)&s_st[h] = raw[j];
+            } else {
+                for (int m = 0; m < nv; ++m) s_st[h + m] = (S)(raw[j] >> (8 * m));
+            }
+        }
+    }
+    // Halo: the +x column, the +y row and (3D) the +z layer of the tile.
+    {
+        constexpr int HX = TY * TZ, HY = TX * TZ, HZ = (DIM == 3) ? TX * TY : 0;
+        constexpr int NHALO = HX + HY + HZ;
+        constexpr int HPT = (NHALO + 255) / 256;
+        S hv[HPT];
+        int hh[HPT];
+#pragma unroll
+        for (int u = 0; u < HPT; ++u) {
+            const int c = tid + 256 * u;
+            hh[u] = -1;
+            int hx = 0, hy = 0, hz = 0;
+            if (c < HX) {
+                hx = ex;
+                hy = c % TY;
+                hz = c / TY;
+            } else if (c < HX + HY) {
+                hx = (c - HX) % TX;
+                hy = ey;
+                hz = (c - HX) / TX;
+            } else if (c < NHALO) {
+                hx = (c - HX - HY) % TX;
+                hy = (c - HX - HY) / TX;
+                hz = ez;
+            } else {
+                continue;
+            }
+            if (hx > ex || hy > ey || hz > ((DIM == 3) ? ez : 0)) continue;
+            if ((c >= HX && hx >= ex) || (c >= HX + HY && hy >= ey) || (c < HX && hy >= ey) ||
+                (DIM == 3 && c < HX + HY && hz >= ez))
+                continue;
+            int gx = x0 + hx, gy = y0 + hy, gz = z0 + hz;
+            if (gx >= L) gx -= L;
+            if (gy >= L) gy -= L;
+            if (DIM == 3 && gz >= L) gz -= L;
+            const uint32_t gi = (uint32_t)gx + (uint32_t)L * ((uint32_t)gy + (uint32_t)L * (uint32_t)gz);
+            hv[u] = ((const S *)d.state)[gi];
+            hh[u] = hx + SX * (hy + SY * hz);
+        }
+#pragma unroll
+        for (int u = 0; u < HPT; ++u) {
+            if (hh[u] < 0) continue;
+            if (IS_XY) {
+                double sv, cv;
+                sincos((double)hv[u] - phi, &sv, &cv);
+                s_sig[hh[u]] = make_double2(cv, sv);
+            } else {
+                s_st[hh[u]] = hv[u];
+            }
         }
     }
     __syncthreads();
@@ -400,39 +508,87 @@ __global__ void __launch_bounds__(256) k_bond(const InstDesc *__restrict__ descs
     if (!full) return;
     __syncthreads();  // s_par initialised and s_bond complete
 
-    // ---- (2) local labelling: union-find over the tile's internal bonds ------
-#pragma unroll
-    for (int j = 0; j < QPT; ++j) {
-        const int qid = tid + 256 * j;
-        if (qid >= NQ) continue;
-        const int qx = qid % QX, row = qid / QX;
-        const int ly = row % TY, lz = row / TY;
-        const int lx0 = qx * 4;
-        if (ly >= ey || lz >= ez || lx0 >= ex) continue;
-        const int nv = min(4, ex - lx0);
-        for (int m = 0; m < nv; ++m) {
-            const uint32_t b = (qb[j] >> (8 * m)) & 0xffu;
-            if (!b) continue;
-            const int lx = lx0 + m;
-            const int l = lx + TX * (ly + TY * lz);
-            if (b & 1u) {
-                if (lx + 1 < ex) lds_union(s_par, l, l + 1);
-                else if (d.tiles[0] == 1) lds_union(s_par, l, l - lx);
+    // ---- (2) local labelling: a row-by-row scan per wavefront ------------------
+    // Lane c of a wavefront owns column c of the tile; each of the four waves
+    // scans its own block of R rows (row r = y + TY z) in order.  In a row the
+    // x bonds form runs (ballot + bit tricks); a run takes the label of its
+    // leftmost site bonded to the row above (or, in 3D, the plane behind) and
+    // otherwise its own start index.  A bonded neighbour whose label differs
+    // from its run's label records an equivalence in s_par (union-find, larger
+    // root under smaller).  Bonds across wave blocks and periodic bonds inside
+    // a tile that spans the lattice are added as equivalences afterwards, and
+    // the root of every site is s_par[s_plab[l]] once s_par is compressed.
+    constexpr int R = (TY * TZ) / 4;
+    constexpr int NONE = 0x7fffffff;
+    {
+        const int lane = tid & 63, wv = tid >> 6;
+        const int c = lane;
+        const int r0 = wv * R;
+        int prevlab = NONE;
+        uint32_t prevb = 0;
+        for (int r = r0; r < r0 + R; ++r) {
+            const int y = r % TY, z = r / TY;
+            if (y >= ey || z >= ez) {  // ragged tile: rows past the lattice edge
+                prevlab = NONE;
+                prevb = 0;
+                continue;
             }
-            if (b & 2u) {
-                if (ly + 1 < ey) lds_union(s_par, l, l + TX);
-                else if (d.tiles[1] == 1) lds_union(s_par, l, l - TX * ly);
+            const int l = c + TX * r;
+            const bool vc = c < ex;
+            const uint32_t b = vc ? s_bond[l] : 0u;
+            const unsigned long long xb = __ballot(vc && (b & 1u) && c + 1 < ex);
+            const unsigned long long brk = ~(xb << 1);          // bit c: a run starts at c
+            const unsigned long long upto = (c == 63) ? ~0ull : ((2ull << c) - 1ull);
+            const int rs = 63 - __clzll((long long)(brk & upto));
+            const unsigned long long ends = ~xb;                // bit c: a run ends at c
+            const int re = __ffsll((long long)(ends & ~((1ull << c) - 1ull))) - 1;
+            int ca = NONE, cb = NONE;
+            if (y > 0 && r - 1 >= r0 && (prevb & 2u)) ca = prevlab;
+            if (DIM == 3 && z > 0 && r - TY >= r0 && (s_bond[l - TX * TY] & 4u)) cb = s_plab[l - TX * TY];
+            const int cand = vc ? min(ca, cb) : NONE;
+            const unsigned long long conn = __ballot(cand != NONE);
+            const unsigned long long mr = conn >> rs;
+            const int f = mr ? rs + __ffsll((long long)mr) - 1 : 64;
+            const int fl = __shfl(cand, f & 63, 64);
+            const int lab = (f <= re) ? fl : rs + TX * r;
+            if (vc) {
+                if (ca != NONE && ca != lab) lds_union(s_par, ca, lab);
+                if (cb != NONE && cb != lab) lds_union(s_par, cb, lab);
+                s_plab[l] = (int16_t)lab;
             }
-            if (DIM == 3 && (b & 4u)) {
-                if (lz + 1 < ez) lds_union(s_par, l, l + TX * TY);
-                else if (d.tiles[2] == 1) lds_union(s_par, l, l - TX * TY * lz);
+            prevlab = lab;
+            prevb = b;
+        }
+    }
+    __syncthreads();
+    // bonds between wave blocks and periodic bonds inside a tile spanning L
+    {
+        const int lane = tid & 63, wv = tid >> 6;
+        const int c = lane;
+        const int r0 = wv * R;
+        if (c < ex) {
+            for (int r = r0; r < r0 + R; ++r) {
+                const int y = r % TY, z = r / TY;
+                if (y >= ey || z >= ez) continue;
+                const int l = c + TX * r;
+                const uint32_t b = s_bond[l];
+                // the row above lies in the previous wave's block
+                if (y > 0 && r - 1 < r0 && (s_bond[l - TX] & 2u)) lds_union(s_par, s_plab[l - TX], s_plab[l]);
+                // the plane behind lies in an earlier wave's block
+                if (DIM == 3 && z > 0 && r - TY < r0 && (s_bond[l - TX * TY] & 4u))
+                    lds_union(s_par, s_plab[l - TX * TY], s_plab[l]);
+                if ((b & 1u) && c + 1 == ex && d.tiles[0] == 1) lds_union(s_par, s_plab[l], s_plab[l - c]);
+                if ((b & 2u) && y + 1 == ey && d.tiles[1] == 1) lds_union(s_par, s_plab[l], s_plab[l - TX * y]);
+                if (DIM == 3 && (b & 4u) && z + 1 == ez && d.tiles[2] == 1)
+                    lds_union(s_par, s_plab[l], s_plab[l - TX * TY * z]);
             }
         }
     }
     __syncthreads();
-    // compress: every site points straight at its tile-local root
     for (int l = tid; l < T; l += 256) s_par[l] = lds_find(s_par, l);
     __syncthreads();
+    // root (tile-local index) of site l
+    auto root_of = [&](int l) -> int { return s_par[s_plab[l]]; };
 
     auto gidx = [&](int r) -> uint32_t {
         const int rx = r % TX, ry = (r / TX) % TY, rz = r / (TX * TY);
@@ -453,7 +609,11 @@ __global__ void __launch_bounds__(256) k_bond(const InstDesc *__restrict__ descs
                              (uint32_t)L * ((uint32_t)(y0 + ly) + (uint32_t)L * (uint32_t)(z0 + lz));
         const int l0 = lx0 + TX * (ly + TY * lz);
         bool anyroot = false;
-        for (int m = 0; m < nv; ++m) anyroot |= (s_par[l0 + m] == l0 + m);
+        int rq[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) rq[m] = (m < nv) ? root_of(l0 + m) : -1;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) anyroot |= (rq[m] == l0 + m);
         uint4 c1 = make_uint4(0, 0, 0, 0), c2 = c1;
         const bool straddle = ((gi0 & 3u) + (uint32_t)nv) > 4u;
         if (anyroot) {
@@ -467,7 +627,7 @@ __global__ void __launch_bounds__(256) k_bond(const InstDesc *__restrict__ descs
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
             if (m >= nv) continue;
-            const int r = s_par[l0 + m];
+            const int r = rq[m];
             if (r == l0 + m) {
                 const uint32_t wd = cw[m];
                 const uint32_t dec = (MODEL == POTTS) ? (uint32_t)(((uint64_t)wd * (uint64_t)d.q) >> 32)
@@ -522,8 +682,8 @@ __global__ void __launch_bounds__(256) k_bond(const InstDesc *__restrict__ descs
                 fi[kk] = -1;
                 continue;
             }
-            fo[kk] = ((s_bond[lo] >> mu) & 1u) ? (int32_t)gidx(s_par[lo]) : -1;
-            fi[kk] = (int32_t)gidx(s_par[li]);
+            fo[kk] = ((s_bond[lo] >> mu) & 1u) ? (int32_t)gidx(root_of(lo)) : -1;
+            fi[kk] = (int32_t)gidx(root_of(li));
         }
     }
 }
@@ -643,7 +803,7 @@ __global__ void __launch_bounds__(256) k_flip(const InstDesc *__restrict__ descs
         __syncthreads();
     }
     const double phi = (MODEL == XY) ? s_phi : 0.0;
-    const uint32_t *lab = d.label;
+    uint32_t *lab = d.label;
 #pragma unroll
     for (int j = 0; j < QPT; ++j) {
         const int qid = tid + 256 * j;
@@ -667,9 +827,23 @@ __global__ void __launch_bounds__(256) k_flip(const InstDesc *__restrict__ descs
             for (int m = 0; m < 4; ++m) v[m] = (m < nv) ? lab[gi0 + m] : ROOT_FLAG;
         }
         uint32_t dec[4];
+#pragma unroll
         for (int m = 0; m < 4; ++m) {
             uint32_t x = v[m];
-            while (!(x & ROOT_FLAG)) x = lab[x];
+            if (!(x & ROOT_FLAG)) {
+                // x is the tile-local root; follow the links the merge made and
+                // point x straight at the final root for the sites after us
+                const uint32_t r = x;
+                uint32_t g = r;
+                x = lab[r];
+                if (!(x & ROOT_FLAG)) {
+                    while (!(x & ROOT_FLAG)) {
+                        g = x;
+                        x = lab[g];
+                    }
+                    if (lab[r] != g) lab[r] = g;
+                }
+            }
             dec[m] = x & 0xffu;
         }
         if (MODEL == ISING || MODEL == POTTS) {
@@ -732,10 +906,10 @@ __global__ void k_advance(InstDesc *descs, int ninst)
 // ---------------------------------------------------------------------------
 // Variant table and launchers.
 // ---------------------------------------------------------------------------
-#define SW_VARIANTS_ISING2 X(0, 128, 32, 1) X(1, 64, 64, 1) X(2, 256, 16, 1)
-#define SW_VARIANTS_ISING3 X(0, 32, 16, 8) X(1, 16, 16, 16) X(2, 64, 8, 8)
-#define SW_VARIANTS_XY2 X(0, 64, 32, 1) X(1, 32, 32, 1) X(2, 128, 16, 1)
-#define SW_VARIANTS_XY3 X(0, 16, 16, 8) X(1, 32, 8, 8) X(2, 16, 8, 8)
+#define SW_VARIANTS_ISING2 X(0, 64, 64, 1) X(1, 64, 32, 1) X(2, 64, 128, 1)
+#define SW_VARIANTS_ISING3 X(0, 64, 8, 8) X(1, 64, 4, 8) X(2, 64, 8, 16)
+#define SW_VARIANTS_XY2 X(0, 64, 32, 1) X(1, 64, 16, 1) X(2, 64, 64, 1)
+#define SW_VARIANTS_XY3 X(0, 64, 4, 8) X(1, 64, 8, 4) X(2, 64, 4, 4)
 
 int num_tile_variants(int, int) { return 3; }
 

@@ -1,0 +1,83 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads and
+exports every function include/sw.h declares, and the binding knows them all;
+plus the host-only workload recipes."""
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "sw.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = set(re.findall(r"\b(sw_[a-z_]+)\s*\(", src))
+    return names
+
+
+def test_header_declares_core_calls():
+    names = declared_functions()
+    for n in ("sw_create", "sw_sweep", "sw_measure", "sw_destroy", "sw_batch_create",
+              "sw_server_submit", "sw_server_poll"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    import ctypes
+    import paper_1403_7560_amd as sw
+    lib = ctypes.CDLL(sw.LIB_PATH)
+    names = declared_functions()
+    missing = [n for n in sorted(names) if not hasattr(lib, n)]
+    assert not missing, missing
+    assert names == set(sw.SIGNATURES), sorted(names ^ set(sw.SIGNATURES))
+    sw.lib()  # argtypes/restype setup succeeds for all of them
+
+
+def test_footprint_is_host_logic():
+    import paper_1403_7560_amd as sw
+    f2 = sw.footprint(sw.ISING, 2, 4096)
+    assert f2 >= 4096 * 4096 * 6
+    assert sw.footprint(sw.XY, 3, 128, 0) > sw.footprint(sw.ISING, 3, 128)
+    with pytest.raises(sw.SWError):
+        sw.footprint(sw.POTTS, 2, 64, 1)
+
+
+def test_job_mix_recipe():
+    from paper_1403_7560_amd import inputs
+    jobs = inputs.job_mix(4000, rate=200.0, seed=3)
+    t = np.array([j["arrival"] for j in jobs])
+    assert np.all(np.diff(t) > 0)
+    assert abs(len(jobs) / t[-1] - 200.0) < 15.0
+    cats = np.array([(j["model"], j["dim"]) for j in jobs])
+    for c in [(0, 2), (1, 2), (0, 3), (2, 3)]:
+        frac = np.mean(np.all(cats == c, axis=1))
+        assert 0.2 < frac < 0.3
+    for j in jobs:
+        lo, hi = (32, 2048) if j["dim"] == 2 else (16, 192)
+        assert lo <= j["L"] <= hi and 100 <= j["sweeps"] <= 5000
+        if j["model"] == 1:
+            assert j["q"] in (3, 4, 10)
+    L2 = np.log([j["L"] for j in jobs if j["dim"] == 2])
+    assert abs(L2.mean() - 0.5 * (math.log(32) + math.log(2048))) < 0.1
+
+
+def test_workload_temperatures():
+    from paper_1403_7560_amd import inputs
+    lats, n = inputs.workload("C4")
+    T = np.array([1 / j["beta"] for j in lats])
+    assert len(lats) == 32 and n == 2000
+    assert T[0] == pytest.approx(0.95 * 2.2019) and T[-1] == pytest.approx(1.05 * 2.2019)
+    assert np.allclose(np.diff(T), np.diff(T)[0])
+    lats, _ = inputs.workload("C2-potts")
+    assert lats[0]["beta"] == pytest.approx(math.log(1 + math.sqrt(3)))
+
+
+def test_bench_refuses_several_gpus():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True)
+    assert r.returncode == 2 and "one GPU" in r.stderr
