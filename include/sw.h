@@ -19,9 +19,14 @@
  *   labels      int32, minimum site index of the cluster.
  *   random      Philox4x32-10; word w of stream (tag, sweep n) of replica r
  *               is lane w%4 of Philox(counter=(w/4, n, tag, r),
- *               key=(seed mod 2^32, seed div 2^32)); tags: bond x/y/z = 0/1/2,
- *               cluster = 3, global = 4, init = 5.  The sweep index n is
- *               0-based and cumulative over calls.
+ *               key=(seed mod 2^32, seed div 2^32)); tags: bond 0, bond z 1,
+ *               bond tie 2, cluster 3, global 4, init 5.  The sweep index n is
+ *               0-based and cumulative over calls.  The 32-bit uniform of bond
+ *               (i, mu) is P*2^16 + S: P = high (x) / low (y) half of word i of
+ *               tag 0, or for z the high (i even) / low (i odd) half of word
+ *               i/2 of tag 1; S = high half of word dim*i+mu of tag 2.  A
+ *               cluster labelled g takes bit g%32 of word g/32 of tag 3
+ *               (Ising, XY, Potts q=2) or word g of tag 3 (Potts q>=3).
  *   couplings   J = k_B = 1, beta = 1/T.  Bond probability: Ising
  *               1-exp(-2 beta) (Sec. 2, step (1)), Potts 1-exp(-beta), XY
  *               1-exp(-2 beta sigma_i sigma_j) on the projections

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libsworacle.so")
 SRC = os.path.join(HERE, "sw_oracle.c")
 
 ISING, POTTS, XY = 0, 1, 2
-TAG_BOND_X, TAG_BOND_Y, TAG_BOND_Z, TAG_CLUSTER, TAG_GLOBAL, TAG_INIT = range(6)
+TAG_BOND, TAG_BOND_Z, TAG_BOND_TIE, TAG_CLUSTER, TAG_GLOBAL, TAG_INIT = range(6)
 STATE_DTYPE = {ISING: np.int8, POTTS: np.uint8, XY: np.float32}
 
 
@@ -45,6 +45,10 @@ def lib():
         L.swo_philox4x32_10.argtypes = [vp, vp, vp]
         L.swo_word.argtypes = [u64, u32, u32, u32, u64]
         L.swo_word.restype = u32
+        L.swo_bond_uniform.argtypes = [u64, u32, u32, i32, u64, i32]
+        L.swo_bond_uniform.restype = u32
+        L.swo_cluster_decision.argtypes = [i32, i32, u64, u32, u32, u64]
+        L.swo_cluster_decision.restype = u32
         L.swo_threshold.argtypes = [i32, dbl]
         L.swo_threshold.restype = u64
         L.swo_init_state.argtypes = [i32, i32, i32, i32, u64, u32, vp]
@@ -77,6 +81,14 @@ def philox(ctr, key):
 
 def word(seed, rep, tag, sweep, w):
     return int(lib().swo_word(seed, rep, tag, sweep, w))
+
+
+def bond_uniform(seed, rep, sweep, dim, i, mu):
+    return int(lib().swo_bond_uniform(seed, rep, sweep, dim, i, mu))
+
+
+def cluster_decision(model, q, seed, rep, sweep, g):
+    return int(lib().swo_cluster_decision(model, q, seed, rep, sweep, g))
 
 
 def threshold(model, beta):

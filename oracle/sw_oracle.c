@@ -33,7 +33,14 @@
  *       allows any generator).  Word w of stream (tag, n) for replica r and
  *       seed s is output lane (w mod 4) of Philox(counter = (w div 4, n, tag,
  *       r), key = (s mod 2^32, s div 2^32)).  n is the 0-based sweep index,
- *       cumulative over calls.
+ *       cumulative over calls.  Tags: BOND 0, BOND_Z 1, BOND_TIE 2,
+ *       CLUSTER 3, GLOBAL 4, INIT 5.  The uniform of bond (i, mu) is the
+ *       32-bit number U = P * 2^16 + S: the primary P is the high (x) or low
+ *       (y) half of word i of BOND, or for z the high (i even) or low (i
+ *       odd) half of word i/2 of BOND_Z; the secondary S is the high half of
+ *       word d*i + mu of BOND_TIE.  Cluster decisions: Ising, XY and Potts
+ *       with q = 2 take bit (g mod 32) of word g/32 of CLUSTER for the
+ *       cluster labelled g; Potts with q >= 3 takes word g of CLUSTER.
  *   R8  a bond is active iff the pair is aligned and u < p with strict <;
  *       u = word * 2^-32, compared exactly as the integer test word < thr
  *       with thr = floor(p * 2^32).
@@ -83,6 +90,31 @@ uint32_t swo_word(uint64_t seed, uint32_t rep, uint32_t tag, uint32_t sweep, uin
     uint32_t out[4];
     swo_philox4x32_10(ctr, key, out);
     return out[w & 3u];
+}
+
+uint32_t swo_bond_uniform(uint64_t seed, uint32_t rep, uint32_t sweep, int dim, uint64_t i, int mu)
+{
+    uint32_t p;
+    if (mu < 2) {
+        uint32_t w = swo_word(seed, rep, SWO_TAG_BOND, sweep, i);
+        p = (mu == 0) ? (w >> 16) : (w & 0xffffu);
+    } else {
+        uint32_t w = swo_word(seed, rep, SWO_TAG_BOND_Z, sweep, i >> 1);
+        p = (i & 1) ? (w & 0xffffu) : (w >> 16);
+    }
+    uint32_t s = swo_word(seed, rep, SWO_TAG_BOND_TIE, sweep, (uint64_t)dim * i + (uint64_t)mu) >> 16;
+    return (p << 16) | s;
+}
+
+uint32_t swo_cluster_decision(int model, int q, uint64_t seed, uint32_t rep, uint32_t sweep,
+                              uint64_t g)
+{
+    if (model == SWO_POTTS && q > 2) {
+        uint32_t w = swo_word(seed, rep, SWO_TAG_CLUSTER, sweep, g);
+        return (uint32_t)(((uint64_t)w * (uint64_t)q) >> 32);
+    }
+    uint32_t w = swo_word(seed, rep, SWO_TAG_CLUSTER, sweep, g >> 5);
+    return (w >> (g & 31u)) & 1u;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -186,7 +218,7 @@ int64_t swo_bonds(int model, int dim, int L, int q, double beta, uint64_t seed, 
         uint8_t b = 0;
         for (int mu = 0; mu < dim; ++mu) {
             int64_t j = neighbour(dim, L, i, mu);
-            uint32_t w = swo_word(seed, rep, (uint32_t)(SWO_TAG_BOND_X + mu), sweep, (uint64_t)i);
+            uint32_t w = swo_bond_uniform(seed, rep, sweep, dim, (uint64_t)i, mu);
             int on;
             if (model == SWO_ISING) {
                 const int8_t *s = (const int8_t *)state;
@@ -282,9 +314,9 @@ void swo_labels_bfs(int dim, int L, const uint8_t *bonds, int32_t *labels)
 }
 
 /* ------------------------------------------------------------------------ */
-/* Step (3): every cluster is set to a random state (R5).  The random word of */
-/* a cluster is the CLUSTER-stream word numbered by its label (its minimum    */
-/* site index), so all sites of the cluster see the same outcome.             */
+/* Step (3): every cluster is set to a random state (R5).  The decision of a */
+/* cluster is drawn from the CLUSTER stream at its label (its minimum site    */
+/* index, R7), so all sites of the cluster see the same outcome.              */
 /*   Ising: +1 or -1.  Potts: uniform in [0,q).                               */
 /*   XY: with probability 1/2 the cluster is reflected in the line normal to  */
 /*   the direction phi, s -> s - 2 (s.r) r, i.e. theta -> pi + 2 phi - theta, */
@@ -307,12 +339,12 @@ void swo_set_clusters(int model, int dim, int L, int q, uint64_t seed, uint32_t 
     int64_t N = num_sites(dim, L);
     double phi = (model == SWO_XY) ? swo_xy_phi(seed, rep, sweep) : 0.0;
     for (int64_t i = 0; i < N; ++i) {
-        uint32_t w = swo_word(seed, rep, SWO_TAG_CLUSTER, sweep, (uint64_t)labels[i]);
+        uint32_t dec = swo_cluster_decision(model, q, seed, rep, sweep, (uint64_t)labels[i]);
         if (model == SWO_ISING) {
-            ((int8_t *)state)[i] = (w >> 31) ? (int8_t)-1 : (int8_t)1;
+            ((int8_t *)state)[i] = dec ? (int8_t)-1 : (int8_t)1;
         } else if (model == SWO_POTTS) {
-            ((uint8_t *)state)[i] = (uint8_t)(((uint64_t)w * (uint64_t)q) >> 32);
-        } else if (w >> 31) {
+            ((uint8_t *)state)[i] = (uint8_t)dec;
+        } else if (dec) {
             float *th = (float *)state;
             th[i] = xy_reflect(th[i], phi);
         }

@@ -169,6 +169,8 @@ struct Lattice {
         d.nslots = nslots;
         d.N = N;
         d.thr = (model == XY) ? 0 : bond_threshold(model, beta);
+        d.thr_hi = (uint32_t)(d.thr >> 16);
+        d.thr_lo = (uint32_t)(d.thr & 0xffffu);
         d.two_beta = 2.0 * beta;
         d.key0 = (uint32_t)(seed & 0xffffffffu);
         d.key1 = (uint32_t)(seed >> 32);
@@ -287,7 +289,7 @@ struct Lattice {
                 if (ev) HIPCHK(hipEventRecord(ev[0], stream));
                 HIPCHK(launch_bond(model, dim, variant, d_solo, d_tmap, ntiles, (uint32_t)k, 0, stream));
                 if (ev) HIPCHK(hipEventRecord(ev[1], stream));
-                HIPCHK(launch_merge(dim, d_solo, d_tmap, ntiles, (uint32_t)k, 0, model, variant, stream));
+                HIPCHK(launch_merge(dim, model, variant, d_solo, d_tmap, ntiles, (uint32_t)k, stream));
                 if (ev) HIPCHK(hipEventRecord(ev[2], stream));
                 HIPCHK(launch_flip(model, dim, variant, d_solo, d_tmap, ntiles, (uint32_t)k, stream));
                 if (ev) HIPCHK(hipEventRecord(ev[3], stream));
@@ -319,7 +321,7 @@ struct Lattice {
         HIPCHK(hipMemcpyAsync(d_solo, &d, sizeof(d), hipMemcpyHostToDevice, stream));
         HIPCHK(hipStreamSynchronize(stream));
         HIPCHK(launch_bond(model, dim, variant, d_solo, d_tmap, ntiles, 0, 1, stream));
-        HIPCHK(launch_merge(dim, d_solo, d_tmap, ntiles, 0, 1, model, variant, stream));
+        HIPCHK(launch_reduce(model, d_solo, d_tmap, ntiles, stream));
         row.assign(nslots, 0);
         HIPCHK(hipMemcpyAsync(row.data(), rec + rec_cap * nslots, (size_t)nslots * 8, hipMemcpyDeviceToHost,
                               stream));
@@ -503,7 +505,7 @@ struct sw_batch_s {
             for (const Group &g : groups)
                 HIPCHK(launch_bond(g.model, g.dim, g.variant, d_desc, g.d_tmap, g.ntiles, (uint32_t)k, 0, stream));
             for (const Group &g : groups)
-                HIPCHK(launch_merge(g.dim, d_desc, g.d_tmap, g.ntiles, (uint32_t)k, 0, g.model, g.variant, stream));
+                HIPCHK(launch_merge(g.dim, g.model, g.variant, d_desc, g.d_tmap, g.ntiles, (uint32_t)k, stream));
             for (const Group &g : groups)
                 HIPCHK(launch_flip(g.model, g.dim, g.variant, d_desc, g.d_tmap, g.ntiles, (uint32_t)k, stream));
         }
@@ -737,7 +739,7 @@ struct sw_server_s {
                 for (const Group &g : groups)
                     HIPCHK(launch_bond(g.model, g.dim, g.variant, d_desc, g.d_tmap, g.ntiles, (uint32_t)k, 0, stream));
                 for (const Group &g : groups)
-                    HIPCHK(launch_merge(g.dim, d_desc, g.d_tmap, g.ntiles, (uint32_t)k, 0, g.model, g.variant, stream));
+                    HIPCHK(launch_merge(g.dim, g.model, g.variant, d_desc, g.d_tmap, g.ntiles, (uint32_t)k, stream));
                 for (const Group &g : groups)
                     HIPCHK(launch_flip(g.model, g.dim, g.variant, d_desc, g.d_tmap, g.ntiles, (uint32_t)k, stream));
             }

@@ -7,7 +7,7 @@
 namespace swmc {
 
 enum { ISING = 0, POTTS = 1, XY = 2 };
-enum { TAG_BOND_X = 0, TAG_BOND_Y = 1, TAG_BOND_Z = 2, TAG_CLUSTER = 3, TAG_GLOBAL = 4,
+enum { TAG_BOND = 0, TAG_BOND_Z = 1, TAG_BOND_TIE = 2, TAG_CLUSTER = 3, TAG_GLOBAL = 4,
        TAG_INIT = 5 };
 
 // A label word is either the global index of the site's parent (< 2^31) or,
@@ -23,6 +23,8 @@ struct InstDesc {
     int32_t nslots;       // measurement slots per record
     int64_t N;
     uint64_t thr;         // Ising / Potts bond threshold floor(p 2^32)
+    uint32_t thr_hi;      // thr >> 16 (0 .. 65536), compared with the 16-bit primaries
+    uint32_t thr_lo;      // thr & 0xffff, compared with the secondary on a tie
     double two_beta;      // XY: 2 beta
     uint32_t key0, key1, rep;
     // schedule of the current launch chain: sweep sweep0 + k runs while k < count
@@ -57,8 +59,9 @@ int slots_for(int model, int q);
 hipError_t launch_init(const InstDesc *d_desc, int inst, const InstDesc &h, hipStream_t s);
 hipError_t launch_bond(int model, int dim, int variant, const InstDesc *d_desc,
                        const int2 *d_tmap, int ntiles, uint32_t k, int mode, hipStream_t s);
-hipError_t launch_merge(int dim, const InstDesc *d_desc, const int2 *d_tmap, int ntiles,
-                        uint32_t k, int mode, int variant_model, int variant, hipStream_t s);
+hipError_t launch_merge(int dim, int model, int variant, const InstDesc *d_desc, const int2 *d_tmap,
+                        int ntiles, uint32_t k, hipStream_t s);
+hipError_t launch_reduce(int model, const InstDesc *d_desc, const int2 *d_tmap, int ntiles, hipStream_t s);
 hipError_t launch_flip(int model, int dim, int variant, const InstDesc *d_desc,
                        const int2 *d_tmap, int ntiles, uint32_t k, hipStream_t s);
 hipError_t launch_canon(const InstDesc *d_desc, int inst, int64_t N, int32_t *d_out,

@@ -229,6 +229,85 @@ __global__ void __launch_bounds__(256) k_init(const InstDesc *__restrict__ descs
 }
 
 // ---------------------------------------------------------------------------
+// Helpers of the bond kernel.
+// ---------------------------------------------------------------------------
+#define GLOBAL __attribute__((address_space(1)))
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// Tile handled by this workgroup.  Workgroups are dealt to the 8 XCDs in
+// turn, so slot b's neighbour b+1 runs on another XCD; this ordering keeps
+// consecutive tiles (whose halos overlap) on one XCD and its L2.
+__device__ __forceinline__ int tile_slot()
+{
+    const int nb = (int)gridDim.x, b = (int)blockIdx.x;
+    if (nb & 7) return b;
+    return (b & 7) * (nb >> 3) + (b >> 3);
+}
+
+// Bytes of t that are zero -> bit 7 of that byte set (exact per byte).
+__device__ __forceinline__ uint32_t zero_bytes(uint32_t t)
+{
+    return ~(((t & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | t) & 0x80808080u;
+}
+
+// The 16-bit secondary of bond (g, mu): high half of word d*g+mu of the tie
+// stream; consulted only when the primary equals the threshold's high half.
+__device__ __noinline__ uint32_t bond_secondary(uint32_t key0, uint32_t key1, uint32_t rep, uint32_t n,
+                                                int dim, uint32_t g, int mu)
+{
+    const uint32_t w = (uint32_t)dim * g + (uint32_t)mu;
+    const uint4 b = philox(make_uint4(w >> 2, n, (uint32_t)TAG_BOND_TIE, rep), key0, key1);
+    return lane_of(b, w & 3u) >> 16;
+}
+
+// Primaries (16 bits) of the bonds of sites gi0 .. gi0+3: x and y come from
+// word g of BOND (high and low half), z from word g/2 of BOND_Z (high half for
+// even g, low half for odd g).
+template <int DIM>
+__device__ __forceinline__ void quad_primaries(const InstDesc &d, uint32_t n, uint32_t gi0, int nv,
+                                               uint32_t px[4], uint32_t py[4], uint32_t pz[4])
+{
+    const uint32_t b0 = gi0 >> 2;
+    const uint4 a = philox(make_uint4(b0, n, (uint32_t)TAG_BOND, d.rep), d.key0, d.key1);
+    uint32_t w[4];
+    if ((gi0 & 3u) == 0) {
+        w[0] = a.x;
+        w[1] = a.y;
+        w[2] = a.z;
+        w[3] = a.w;
+    } else {
+        uint4 b = a;
+        if ((gi0 & 3u) + (uint32_t)nv > 4u)
+            b = philox(make_uint4(b0 + 1u, n, (uint32_t)TAG_BOND, d.rep), d.key0, d.key1);
+        quad_words(gi0, a, b, w);
+    }
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        px[m] = w[m] >> 16;
+        py[m] = w[m] & 0xffffu;
+    }
+    if (DIM == 3) {
+        // z words g/2 for g = gi0 .. gi0+3 lie in blocks gi0/8 and possibly gi0/8 + 1
+        const uint32_t zb0 = gi0 >> 3;
+        const uint4 za = philox(make_uint4(zb0, n, (uint32_t)TAG_BOND_Z, d.rep), d.key0, d.key1);
+        uint4 zb = za;
+        if (((gi0 + (uint32_t)nv - 1u) >> 3) != zb0)
+            zb = philox(make_uint4(zb0 + 1u, n, (uint32_t)TAG_BOND_Z, d.rep), d.key0, d.key1);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const uint32_t g = gi0 + (uint32_t)m;
+            const uint32_t idx = (g >> 1) - (zb0 << 2);  // 0 .. 5
+            const uint32_t word = (idx < 4u) ? lane_of(za, idx) : lane_of(zb, idx - 4u);
+            pz[m] = (g & 1u) ? (word & 0xffffu) : (word >> 16);
+        }
+    } else {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) pz[m] = 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Bond generation + tile-local labelling + measurement.
 // mode 0: full sweep step; mode 1: measurement of the configuration only.
 // ---------------------------------------------------------------------------
@@ -242,27 +321,37 @@ __global__ void __launch_bounds__(256) k_bond(const InstDesc *__restrict__ descs
     constexpr int NH = SX * SY * SZ;
     constexpr int QX = TX / 4;
     constexpr int NQ = T / 4;
-    constexpr int QPT = (NQ + 255) / 256;
+    constexpr int QPT = NQ / 256;
+    constexpr int ROWS = TY * TZ;
+    constexpr int R = ROWS / 4;  // rows scanned by each wavefront
     constexpr bool IS_XY = (MODEL == XY);
-    static_assert(TX % 4 == 0, "quads along x");
+    constexpr int QCAP = 256;    // per-wave queue of deferred equivalences
     static_assert(TX == 64, "a tile row is one wavefront (lane = column) in the labelling scan");
     static_assert(T <= 32768, "provisional labels are 16-bit");
-    static_assert((TY * TZ) % 4 == 0, "whole rows per wavefront");
+    static_assert(ROWS % 4 == 0, "whole rows per wavefront");
     static_assert(NQ % 256 == 0, "whole quads per thread");
     static_assert(DIM == 3 || TZ == 1, "2D tiles have TZ = 1");
 
-    __shared__ __align__(16) S s_st[IS_XY ? 4 : NH];
-    __shared__ double2 s_sig[IS_XY ? NH : 1];  // (cos, sin) of theta - phi
-    __shared__ int s_par[T];         // equivalence table over provisional labels
-    __shared__ int16_t s_plab[T];    // provisional label of every site
-    __shared__ uint8_t s_bond[T];
+    // LDS: the staged states (or XY projections) are dead once the bonds are
+    // known, so the labelling arrays reuse that space.
+    constexpr int STAGE_BYTES = IS_XY ? NH * 16 : ((NH + 15) / 16) * 16;
+    constexpr int LABEL_BYTES = T * 4 + T * 2;
+    constexpr int REGION = STAGE_BYTES > LABEL_BYTES ? STAGE_BYTES : LABEL_BYTES;
+    __shared__ __align__(16) uint8_t s_mem[REGION];
+    __shared__ __align__(16) uint8_t s_bond[T];
+    __shared__ uint32_t s_cw[ROWS * 8];  // cluster decision words, 8 per tile row
+    __shared__ uint32_t s_q[4][QCAP];
     __shared__ int s_hist[MODEL == POTTS ? 256 : 1];
     __shared__ double s_red[4][3];
     __shared__ double s_phi;
+    S *s_st = (S *)s_mem;
+    double2 *s_sig = (double2 *)s_mem;
+    int *s_par = (int *)s_mem;
+    int16_t *s_plab = (int16_t *)(s_mem + T * 4);
 
-    const int2 tm = tmap[blockIdx.x];
+    const int2 tm = tmap[tile_slot()];
     if (tm.x < 0) return;
-    const InstDesc &d = descs[tm.x];
+    const InstDesc d = descs[tm.x];
     if (k >= d.count) return;
     const uint32_t n = d.sweep0 + k;
     const int L = d.L;
@@ -273,22 +362,28 @@ __global__ void __launch_bounds__(256) k_bond(const InstDesc *__restrict__ descs
     const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
     const int ex = min(TX, L - x0), ey = min(TY, L - y0), ez = (DIM == 3) ? min(TZ, L - z0) : 1;
     const int tid = threadIdx.x;
+    const int lane = tid & 63, wv = tid >> 6;
     const bool full = (mode == 0);
     const bool meas = (mode == 1) || d.measure;
+    const bool bits_dec = (MODEL != POTTS) || d.q == 2;  // one decision bit per cluster
+    GLOBAL uint8_t *g_bond = (GLOBAL uint8_t *)d.bond;
+    GLOBAL uint32_t *g_label = (GLOBAL uint32_t *)d.label;
+
+    auto gsite = [&](int lx, int ly, int lz) -> uint32_t {
+        return (uint32_t)(x0 + lx) + (uint32_t)L * ((uint32_t)(y0 + ly) + (uint32_t)L * (uint32_t)(z0 + lz));
+    };
 
     if (IS_XY && tid == 0) s_phi = xy_phi(d, n);
     if (MODEL == POTTS && meas)
         for (int c = tid; c < d.q; c += 256) s_hist[c] = 0;
-    if (full)
-        for (int l = tid; l < T; l += 256) s_par[l] = l;
     if (IS_XY) __syncthreads();
     const double phi = IS_XY ? s_phi : 0.0;
 
     // ---- stage states (+1 halo in every + direction) ------------------------
     // Interior: one 4-site load per quad, all issued before any LDS store.
     {
-        uint32_t raw[QPT];      // Ising / Potts: four states
-        float4 rawf[QPT];       // XY: four angles
+        uint32_t raw[QPT];
+        float4 rawf[QPT];
 #pragma unroll
         for (int j = 0; j < QPT; ++j) {
             const int qid = tid + 256 * j;
@@ -299,19 +394,21 @@ __global__ void __launch_bounds__(256) k_bond(const InstDesc *__restrict__ descs
             rawf[j] = make_float4(0.f, 0.f, 0.f, 0.f);
             if (ly >= ey || lz >= ez || lx0 >= ex) continue;
             const int nv = min(4, ex - lx0);
-            const uint32_t gi0 = (uint32_t)(x0 + lx0) +
-                                 (uint32_t)L * ((uint32_t)(y0 + ly) + (uint32_t)L * (uint32_t)(z0 + lz));
+            const uint32_t gi0 = gsite(lx0, ly, lz);
             if ((gi0 & 3u) == 0 && nv == 4) {
-                if (IS_XY) rawf[j] = *(const float4 *)((const float *)d.state + gi0);
-                else raw[j] = *(const uint32_t *)((const uint8_t *)d.state + gi0);
+                if (IS_XY) {
+                    const f32x4 v = *(const GLOBAL f32x4 *)((const GLOBAL float *)d.state + gi0);
+                    rawf[j] = make_float4(v.x, v.y, v.z, v.w);
+                }
+                else raw[j] = *(const GLOBAL uint32_t *)((const GLOBAL uint8_t *)d.state + gi0);
             } else if (IS_XY) {
-                const float *st = (const float *)d.state + gi0;
+                const GLOBAL float *st = (const GLOBAL float *)d.state + gi0;
                 rawf[j].x = st[0];
                 if (nv > 1) rawf[j].y = st[1];
                 if (nv > 2) rawf[j].z = st[2];
                 if (nv > 3) rawf[j].w = st[3];
             } else {
-                const uint8_t *st = (const uint8_t *)d.state + gi0;
+                const GLOBAL uint8_t *st = (const GLOBAL uint8_t *)d.state + gi0;
                 for (int m = 0; m < nv; ++m) raw[j] |= (uint32_t)st[m] << (8 * m);
             }
         }
@@ -358,27 +455,26 @@ __global__ void __launch_bounds__(256) k_bond(const InstDesc *__restrict__ descs
                 hx = ex;
                 hy = c % TY;
                 hz = c / TY;
+                if (hy >= ey || hz >= ez) continue;
             } else if (c < HX + HY) {
                 hx = (c - HX) % TX;
                 hy = ey;
                 hz = (c - HX) / TX;
+                if (hx >= ex || hz >= ez) continue;
             } else if (c < NHALO) {
                 hx = (c - HX - HY) % TX;
                 hy = (c - HX - HY) / TX;
                 hz = ez;
+                if (hx >= ex || hy >= ey) continue;
             } else {
                 continue;
             }
-            if (hx > ex || hy > ey || hz > ((DIM == 3) ? ez : 0)) continue;
-            if ((c >= HX && hx >= ex) || (c >= HX + HY && hy >= ey) || (c < HX && hy >= ey) ||
-                (DIM == 3 && c < HX + HY && hz >= ez))
-                continue;
             int gx = x0 + hx, gy = y0 + hy, gz = z0 + hz;
             if (gx >= L) gx -= L;
             if (gy >= L) gy -= L;
             if (DIM == 3 && gz >= L) gz -= L;
             const uint32_t gi = (uint32_t)gx + (uint32_t)L * ((uint32_t)gy + (uint32_t)L * (uint32_t)gz);
-            hv[u] = ((const S *)d.state)[gi];
+            hv[u] = ((const GLOBAL S *)d.state)[gi];
             hh[u] = hx + SX * (hy + SY * hz);
         }
 #pragma unroll
@@ -393,6 +489,19 @@ __global__ void __launch_bounds__(256) k_bond(const InstDesc *__restrict__ descs
             }
         }
     }
+    // Cluster decision words of every tile row (one bit per possible root):
+    // row r needs words g/32 for its sites g, which lie in Philox blocks
+    // g_r/128 and g_r/128 + 1 of the cluster stream.
+    if (full && bits_dec && tid < 2 * ROWS) {
+        const int r = tid >> 1, half = tid & 1;
+        const int ly = r % TY, lz = r / TY;
+        if (ly < ey && lz < ez) {
+            const uint32_t gr = gsite(0, ly, lz);
+            const uint4 w = philox(make_uint4((gr >> 7) + (uint32_t)half, n, (uint32_t)TAG_CLUSTER, d.rep),
+                                   d.key0, d.key1);
+            *(uint4 *)&s_cw[8 * r + 4 * half] = w;
+        }
+    }
     __syncthreads();
 
     // ---- (1) bonds and measurement -------------------------------------------
@@ -403,88 +512,120 @@ __global__ void __launch_bounds__(256) k_bond(const InstDesc *__restrict__ descs
     for (int j = 0; j < QPT; ++j) {
         qb[j] = 0;
         const int qid = tid + 256 * j;
-        if (qid >= NQ) continue;
         const int qx = qid % QX, row = qid / QX;
         const int ly = row % TY, lz = row / TY;
         const int lx0 = qx * 4;
         if (ly >= ey || lz >= ez || lx0 >= ex) continue;
         const int nv = min(4, ex - lx0);
-        const uint32_t gi0 = (uint32_t)(x0 + lx0) +
-                             (uint32_t)L * ((uint32_t)(y0 + ly) + (uint32_t)L * (uint32_t)(z0 + lz));
-        uint32_t wq[DIM][4];
-        const bool straddle = ((gi0 & 3u) + (uint32_t)nv) > 4u;
-        if (full) {
+        const uint32_t vmask = (nv == 4) ? 0xffffffffu : ((1u << (8 * nv)) - 1u);
+        const uint32_t gi0 = gsite(lx0, ly, lz);
+        const int h = lx0 + SX * (ly + SY * lz);
+        uint32_t px[4], py[4], pz[4];
+        if (full) quad_primaries<DIM>(d, n, gi0, nv, px, py, pz);
+        uint32_t bq = 0;
+        if constexpr (!IS_XY) {
+            const uint32_t s = *(const uint32_t *)&s_st[h];
+            const uint32_t sn = (uint8_t)s_st[h + 4];
+            const uint32_t sxn = (s >> 8) | (sn << 24);
+            const uint32_t syn = *(const uint32_t *)&s_st[h + SX];
+            const uint32_t eqx = zero_bytes(s ^ sxn) & vmask;
+            const uint32_t eqy = zero_bytes(s ^ syn) & vmask;
+            uint32_t eqz = 0;
+            if (DIM == 3) eqz = zero_bytes(s ^ *(const uint32_t *)&s_st[h + SX * SY]) & vmask;
+            if (meas) {
+                cnt_al += __popc(eqx) + __popc(eqy) + __popc(eqz);
+                if (MODEL == ISING) cnt_m += nv - 2 * __popc(s & 0x80808080u & vmask);
+                else {
 #pragma unroll
-            for (int mu = 0; mu < DIM; ++mu) {
-                const uint4 a = philox(make_uint4(gi0 >> 2, n, (uint32_t)(TAG_BOND_X + mu), d.rep), d.key0, d.key1);
-                uint4 b = a;
-                if (straddle)
-                    b = philox(make_uint4((gi0 >> 2) + 1u, n, (uint32_t)(TAG_BOND_X + mu), d.rep), d.key0, d.key1);
-                quad_words(gi0, a, b, wq[mu]);
+                    for (int m = 0; m < 4; ++m)
+                        if (m < nv) atomicAdd(&s_hist[(s >> (8 * m)) & 0xffu], 1);
+                }
             }
-        }
+            if (full) {
+                const uint32_t th = d.thr_hi;
+                uint32_t tie = 0;
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            if (m >= nv) continue;
-            const int lx = lx0 + m;
-            const int h = lx + SX * (ly + SY * lz);
-            uint32_t b = 0;
+                for (int m = 0; m < 4; ++m) {
+                    const uint32_t ax = (eqx >> (8 * m + 7)) & 1u, ay = (eqy >> (8 * m + 7)) & 1u;
+                    const uint32_t az = (eqz >> (8 * m + 7)) & 1u;
+                    uint32_t bm = (ax & (px[m] < th)) | ((ay & (py[m] < th)) << 1);
+                    if (DIM == 3) bm |= (az & (pz[m] < th)) << 2;
+                    bq |= bm << (8 * m);
+                    tie |= (ax & (px[m] == th)) | (ay & (py[m] == th)) | (az & (pz[m] == th));
+                }
+                if (tie) {  // rare: the primary equals the threshold's high half
 #pragma unroll
-            for (int mu = 0; mu < DIM; ++mu) {
-                const int hn = h + (mu == 0 ? 1 : (mu == 1 ? SX : SX * SY));
-                if (IS_XY) {
-                    const double2 a = s_sig[h], c = s_sig[hn];
+                    for (int m = 0; m < 4; ++m) {
+                        const uint32_t g = gi0 + (uint32_t)m;
+                        const uint32_t p[3] = {px[m], py[m], pz[m]};
+                        const uint32_t eq[3] = {eqx, eqy, eqz};
+#pragma unroll
+                        for (int mu = 0; mu < DIM; ++mu)
+                            if (((eq[mu] >> (8 * m + 7)) & 1u) && p[mu] == th &&
+                                bond_secondary(d.key0, d.key1, d.rep, n, DIM, g, mu) < d.thr_lo)
+                                bq |= 1u << (8 * m + mu);
+                    }
+                }
+            }
+        } else {
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                if (m >= nv) continue;
+                const int hm = h + m;
+                const double2 a = s_sig[hm];
+                if (meas) {
+                    sx_acc += a.x;
+                    sy_acc += a.y;
+                }
+                const uint32_t p[3] = {px[m], py[m], pz[m]};
+#pragma unroll
+                for (int mu = 0; mu < DIM; ++mu) {
+                    const int hn = hm + (mu == 0 ? 1 : (mu == 1 ? SX : SX * SY));
+                    const double2 c = s_sig[hn];
                     if (meas) e_acc -= a.x * c.x + a.y * c.y;
                     if (full) {
-                        const uint32_t wd = wq[mu][m];
+                        // u = (P 2^16 + S) 2^-32 against p = -expm1(-(2 beta s_i) s_j)
                         const double x = (d.two_beta * a.x) * c.x;
-                        const double p = -expm1(-x);
-                        const double u = (double)wd * 0x1p-32;
-                        if (u < p) b |= 1u << mu;
-                    }
-                } else {
-                    const bool al = s_st[h] == s_st[hn];
-                    cnt_al += al;
-                    if (full) {
-                        const uint32_t wd = wq[mu][m];
-                        if (al && (uint64_t)wd < d.thr) b |= 1u << mu;
+                        const double pr = -expm1(-x);
+                        const double lo = (double)p[mu] * 0x1p-16, hi = (double)(p[mu] + 1u) * 0x1p-16;
+                        bool on;
+                        if (hi <= pr) on = true;
+                        else if (lo >= pr) on = false;
+                        else {
+                            const uint32_t sec = bond_secondary(d.key0, d.key1, d.rep, n, DIM, gi0 + (uint32_t)m, mu);
+                            on = (double)((p[mu] << 16) | sec) * 0x1p-32 < pr;
+                        }
+                        if (on) bq |= 1u << (8 * m + mu);
                     }
                 }
             }
-            if (meas) {
-                if constexpr (MODEL == ISING) cnt_m += s_st[h];
-                else if constexpr (MODEL == POTTS) atomicAdd(&s_hist[s_st[h]], 1);
-                else {
-                    sx_acc += s_sig[h].x;
-                    sy_acc += s_sig[h].y;
-                }
-            }
-            if (full) s_bond[lx + TX * (ly + TY * lz)] = (uint8_t)b;
-            qb[j] |= b << (8 * m);
         }
-        if (full && d.store_bonds) {
-            if ((gi0 & 3u) == 0 && nv == 4) {
-                *(uint32_t *)(d.bond + gi0) = qb[j];
-            } else {
-                for (int m = 0; m < nv; ++m) d.bond[gi0 + m] = (uint8_t)(qb[j] >> (8 * m));
+        qb[j] = bq;
+        if (full) {
+            *(uint32_t *)&s_bond[lx0 + TX * (ly + TY * lz)] = bq;
+            if (d.store_bonds) {
+                if ((gi0 & 3u) == 0 && nv == 4) {
+                    *(GLOBAL uint32_t *)(g_bond + gi0) = bq;
+                } else {
+                    for (int m = 0; m < nv; ++m) g_bond[gi0 + m] = (uint8_t)(bq >> (8 * m));
+                }
             }
         }
     }
 
     // ---- measurement partials of this tile -----------------------------------
     if (meas) {
-        const int wv = tid >> 6, ln = tid & 63;
-        int64_t *part = d.part + (int64_t)t * d.nslots;
+        GLOBAL int64_t *part = (GLOBAL int64_t *)d.part + (int64_t)t * d.nslots;
         if (IS_XY) {
             const double a = wave_sum_d(e_acc), b = wave_sum_d(sx_acc), c = wave_sum_d(sy_acc);
-            if (ln == 0) {
+            if (lane == 0) {
                 s_red[wv][0] = a;
                 s_red[wv][1] = b;
                 s_red[wv][2] = c;
             }
         } else {
             const int a = wave_sum_i(cnt_al), b = wave_sum_i(cnt_m);
-            if (ln == 0) {
+            if (lane == 0) {
                 s_red[wv][0] = (double)a;
                 s_red[wv][1] = (double)b;
             }
@@ -506,7 +647,9 @@ __global__ void __launch_bounds__(256) k_bond(const InstDesc *__restrict__ descs
             for (int c = tid; c < d.q; c += 256) part[1 + c] = s_hist[c];
     }
     if (!full) return;
-    __syncthreads();  // s_par initialised and s_bond complete
+    __syncthreads();  // s_bond complete; staged states no longer needed
+    for (int l = tid; l < T; l += 256) s_par[l] = l;
+    __syncthreads();
 
     // ---- (2) local labelling: a row-by-row scan per wavefront ------------------
     // Lane c of a wavefront owns column c of the tile; each of the four waves
@@ -514,16 +657,33 @@ __global__ void __launch_bounds__(256) k_bond(const InstDesc *__restrict__ descs
     // x bonds form runs (ballot + bit tricks); a run takes the label of its
     // leftmost site bonded to the row above (or, in 3D, the plane behind) and
     // otherwise its own start index.  A bonded neighbour whose label differs
-    // from its run's label records an equivalence in s_par (union-find, larger
-    // root under smaller).  Bonds across wave blocks and periodic bonds inside
-    // a tile that spans the lattice are added as equivalences afterwards, and
-    // the root of every site is s_par[s_plab[l]] once s_par is compressed.
-    constexpr int R = (TY * TZ) / 4;
+    // from its run's label is an equivalence, queued and resolved afterwards
+    // in the union-find table s_par (larger root under smaller), together
+    // with the bonds across wave blocks and the periodic bonds inside a tile
+    // that spans the lattice.  The root of site l is then s_par[s_plab[l]].
     constexpr int NONE = 0x7fffffff;
+    int qn = 0;  // entries in this wave's queue (uniform)
+    auto flush = [&]() {
+        for (int e = lane; e < qn; e += 64) {
+            const uint32_t pr = s_q[wv][e];
+            lds_union(s_par, (int)(pr >> 16), (int)(pr & 0xffffu));
+        }
+        qn = 0;
+    };
+    auto push = [&](bool want, int a, int b) {
+        if (qn > QCAP - 64) flush();
+        const unsigned long long m = __ballot(want);
+        if (want) {
+            const int pos = qn + __popcll(m & ((1ull << lane) - 1ull));
+            s_q[wv][pos] = ((uint32_t)a << 16) | (uint32_t)b;
+        }
+        qn += __popcll(m);
+    };
     {
-        const int lane = tid & 63, wv = tid >> 6;
         const int c = lane;
         const int r0 = wv * R;
+        const unsigned long long upto = (c == 63) ? ~0ull : ((2ull << c) - 1ull);
+        const unsigned long long from = ~((1ull << c) - 1ull);
         int prevlab = NONE;
         uint32_t prevb = 0;
         for (int r = r0; r < r0 + R; ++r) {
@@ -537,11 +697,9 @@ __global__ void __launch_bounds__(256) k_bond(const InstDesc *__restrict__ descs
             const bool vc = c < ex;
             const uint32_t b = vc ? s_bond[l] : 0u;
             const unsigned long long xb = __ballot(vc && (b & 1u) && c + 1 < ex);
-            const unsigned long long brk = ~(xb << 1);          // bit c: a run starts at c
-            const unsigned long long upto = (c == 63) ? ~0ull : ((2ull << c) - 1ull);
+            const unsigned long long brk = ~(xb << 1);  // bit c: a run starts at c
             const int rs = 63 - __clzll((long long)(brk & upto));
-            const unsigned long long ends = ~xb;                // bit c: a run ends at c
-            const int re = __ffsll((long long)(ends & ~((1ull << c) - 1ull))) - 1;
+            const int re = __ffsll((long long)(~xb & from)) - 1;
             int ca = NONE, cb = NONE;
             if (y > 0 && r - 1 >= r0 && (prevb & 2u)) ca = prevlab;
             if (DIM == 3 && z > 0 && r - TY >= r0 && (s_bond[l - TX * TY] & 4u)) cb = s_plab[l - TX * TY];
@@ -551,98 +709,107 @@ __global__ void __launch_bounds__(256) k_bond(const InstDesc *__restrict__ descs
             const int f = mr ? rs + __ffsll((long long)mr) - 1 : 64;
             const int fl = __shfl(cand, f & 63, 64);
             const int lab = (f <= re) ? fl : rs + TX * r;
-            if (vc) {
-                if (ca != NONE && ca != lab) lds_union(s_par, ca, lab);
-                if (cb != NONE && cb != lab) lds_union(s_par, cb, lab);
-                s_plab[l] = (int16_t)lab;
-            }
+            if (vc) s_plab[l] = (int16_t)lab;
+            push(vc && ca != NONE && ca != lab, ca, lab);
+            if (DIM == 3) push(vc && cb != NONE && cb != lab, cb, lab);
             prevlab = lab;
             prevb = b;
         }
     }
-    __syncthreads();
+    __syncthreads();  // all provisional labels written
     // bonds between wave blocks and periodic bonds inside a tile spanning L
     {
-        const int lane = tid & 63, wv = tid >> 6;
         const int c = lane;
         const int r0 = wv * R;
-        if (c < ex) {
-            for (int r = r0; r < r0 + R; ++r) {
-                const int y = r % TY, z = r / TY;
-                if (y >= ey || z >= ez) continue;
-                const int l = c + TX * r;
-                const uint32_t b = s_bond[l];
-                // the row above lies in the previous wave's block
-                if (y > 0 && r - 1 < r0 && (s_bond[l - TX] & 2u)) lds_union(s_par, s_plab[l - TX], s_plab[l]);
-                // the plane behind lies in an earlier wave's block
-                if (DIM == 3 && z > 0 && r - TY < r0 && (s_bond[l - TX * TY] & 4u))
-                    lds_union(s_par, s_plab[l - TX * TY], s_plab[l]);
-                if ((b & 1u) && c + 1 == ex && d.tiles[0] == 1) lds_union(s_par, s_plab[l], s_plab[l - c]);
-                if ((b & 2u) && y + 1 == ey && d.tiles[1] == 1) lds_union(s_par, s_plab[l], s_plab[l - TX * y]);
-                if (DIM == 3 && (b & 4u) && z + 1 == ez && d.tiles[2] == 1)
-                    lds_union(s_par, s_plab[l], s_plab[l - TX * TY * z]);
+        const bool vc = c < ex;
+        for (int r = r0; r < r0 + R; ++r) {
+            const int y = r % TY, z = r / TY;
+            if (y >= ey || z >= ez) continue;
+            const int l = c + TX * r;
+            const uint32_t b = vc ? s_bond[l] : 0u;
+            const int own = vc ? s_plab[l] : 0;
+            // the row above lies in the previous wave's block
+            const bool wy = vc && y > 0 && r - 1 < r0 && (s_bond[l - TX] & 2u);
+            push(wy, wy ? s_plab[l - TX] : 0, own);
+            // the plane behind lies in an earlier wave's block
+            if (DIM == 3) {
+                const bool wz = vc && z > 0 && r - TY < r0 && (s_bond[l - TX * TY] & 4u);
+                push(wz, wz ? s_plab[l - TX * TY] : 0, own);
+            }
+            const bool px_ = vc && (b & 1u) && c + 1 == ex && d.tiles[0] == 1;
+            push(px_, px_ ? s_plab[l - c] : 0, own);
+            const bool py_ = vc && (b & 2u) && y + 1 == ey && d.tiles[1] == 1;
+            push(py_, py_ ? s_plab[l - TX * y] : 0, own);
+            if (DIM == 3) {
+                const bool pz_ = vc && (b & 4u) && z + 1 == ez && d.tiles[2] == 1;
+                push(pz_, pz_ ? s_plab[l - TX * TY * z] : 0, own);
             }
         }
+        flush();
     }
     __syncthreads();
     for (int l = tid; l < T; l += 256) s_par[l] = lds_find(s_par, l);
     __syncthreads();
     // root (tile-local index) of site l
     auto root_of = [&](int l) -> int { return s_par[s_plab[l]]; };
-
     auto gidx = [&](int r) -> uint32_t {
         const int rx = r % TX, ry = (r / TX) % TY, rz = r / (TX * TY);
-        return (uint32_t)(x0 + rx) + (uint32_t)L * ((uint32_t)(y0 + ry) + (uint32_t)L * (uint32_t)(z0 + rz));
+        return gsite(rx, ry, rz);
     };
 
     // ---- local roots draw the cluster decision; labels to HBM -----------------
 #pragma unroll
     for (int j = 0; j < QPT; ++j) {
         const int qid = tid + 256 * j;
-        if (qid >= NQ) continue;
         const int qx = qid % QX, row = qid / QX;
         const int ly = row % TY, lz = row / TY;
         const int lx0 = qx * 4;
         if (ly >= ey || lz >= ez || lx0 >= ex) continue;
         const int nv = min(4, ex - lx0);
-        const uint32_t gi0 = (uint32_t)(x0 + lx0) +
-                             (uint32_t)L * ((uint32_t)(y0 + ly) + (uint32_t)L * (uint32_t)(z0 + lz));
+        const uint32_t gi0 = gsite(lx0, ly, lz);
         const int l0 = lx0 + TX * (ly + TY * lz);
-        bool anyroot = false;
+        const uint2 pl = *(const uint2 *)&s_plab[l0];
+        const int p4[4] = {(int)(int16_t)(pl.x & 0xffffu), (int)(int16_t)(pl.x >> 16),
+                           (int)(int16_t)(pl.y & 0xffffu), (int)(int16_t)(pl.y >> 16)};
         int rq[4];
 #pragma unroll
-        for (int m = 0; m < 4; ++m) rq[m] = (m < nv) ? root_of(l0 + m) : -1;
+        for (int m = 0; m < 4; ++m) rq[m] = (m < nv) ? s_par[p4[m]] : -1;
+        bool anyroot = false;
 #pragma unroll
         for (int m = 0; m < 4; ++m) anyroot |= (rq[m] == l0 + m);
-        uint4 c1 = make_uint4(0, 0, 0, 0), c2 = c1;
-        const bool straddle = ((gi0 & 3u) + (uint32_t)nv) > 4u;
+        uint32_t dec[4] = {0u, 0u, 0u, 0u};
         if (anyroot) {
-            c1 = philox(make_uint4(gi0 >> 2, n, (uint32_t)TAG_CLUSTER, d.rep), d.key0, d.key1);
-            c2 = straddle ? philox(make_uint4((gi0 >> 2) + 1u, n, (uint32_t)TAG_CLUSTER, d.rep), d.key0, d.key1)
-                          : c1;
+            if (bits_dec) {
+                const uint32_t gr = gsite(0, ly, lz);
+                const uint32_t base = (gr >> 7) << 2;
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    const uint32_t g = gi0 + (uint32_t)m;
+                    dec[m] = (s_cw[8 * row + (int)((g >> 5) - base)] >> (g & 31u)) & 1u;
+                }
+            } else {
+                const uint4 c1 = philox(make_uint4(gi0 >> 2, n, (uint32_t)TAG_CLUSTER, d.rep), d.key0, d.key1);
+                uint4 c2 = c1;
+                if ((gi0 & 3u) + (uint32_t)nv > 4u)
+                    c2 = philox(make_uint4((gi0 >> 2) + 1u, n, (uint32_t)TAG_CLUSTER, d.rep), d.key0, d.key1);
+                uint32_t cw[4];
+                quad_words(gi0, c1, c2, cw);
+#pragma unroll
+                for (int m = 0; m < 4; ++m) dec[m] = (uint32_t)(((uint64_t)cw[m] * (uint64_t)d.q) >> 32);
+            }
         }
-        uint32_t cw[4];
-        quad_words(gi0, c1, c2, cw);
         uint32_t lab[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
             if (m >= nv) continue;
-            const int r = rq[m];
-            if (r == l0 + m) {
-                const uint32_t wd = cw[m];
-                const uint32_t dec = (MODEL == POTTS) ? (uint32_t)(((uint64_t)wd * (uint64_t)d.q) >> 32)
-                                                      : (wd >> 31);
-                lab[m] = ROOT_FLAG | dec;
-            } else {
-                lab[m] = gidx(r);
-            }
+            lab[m] = (rq[m] == l0 + m) ? (ROOT_FLAG | dec[m]) : gidx(rq[m]);
         }
         if ((gi0 & 3u) == 0 && nv == 4) {
-            *(uint4 *)(d.label + gi0) = make_uint4(lab[0], lab[1], lab[2], lab[3]);
+            *(GLOBAL u32x4 *)(g_label + gi0) = (u32x4){lab[0], lab[1], lab[2], lab[3]};
         } else {
 #pragma unroll
             for (int m = 0; m < 4; ++m)
-                if (m < nv) d.label[gi0 + m] = lab[m];
+                if (m < nv) g_label[gi0 + m] = lab[m];
         }
     }
 
@@ -651,8 +818,8 @@ __global__ void __launch_bounds__(256) k_bond(const InstDesc *__restrict__ descs
     for (int mu = 0; mu < DIM; ++mu) {
         if (d.tiles[mu] == 1) continue;
         const int F = d.face_len[mu];
-        int32_t *fo = d.face + d.face_off[mu] + (int64_t)t * 2 * F;
-        int32_t *fi = fo + F;
+        GLOBAL int32_t *fo = (GLOBAL int32_t *)d.face + d.face_off[mu] + (int64_t)t * 2 * F;
+        GLOBAL int32_t *fi = fo + F;
         const int emu = (mu == 0) ? ex : (mu == 1 ? ey : ez);
         for (int kk = tid; kk < F; kk += 256) {
             int a, b;  // transverse coordinates
@@ -689,56 +856,56 @@ __global__ void __launch_bounds__(256) k_bond(const InstDesc *__restrict__ descs
 }
 
 // ---------------------------------------------------------------------------
-// Global label equivalence across tile faces + reduction of the measurement.
-// grid = (tiles, DIM + 1); slice mu < DIM merges the +mu face of each tile,
-// slice DIM reduces the per-tile partials into the sweep's record row.
+// Global label equivalence across tile faces.  grid = (ceil(tiles * FMAX /
+// 256), DIM): thread e of slice mu handles element e % FMAX of the +mu face of
+// tile slot e / FMAX; for every active bond crossing the face it links the
+// larger of the two tile roots under the smaller with device-scope atomicMin.
 // ---------------------------------------------------------------------------
-template <int MODEL, int DIM>
+template <int DIM>
 __global__ void __launch_bounds__(256) k_merge(const InstDesc *__restrict__ descs,
-                                               const int2 *__restrict__ tmap, uint32_t k, int mode)
+                                               const int2 *__restrict__ tmap, int ntiles, int fmax,
+                                               uint32_t k)
+{
+    const int mu = blockIdx.y;
+    const int e = tile_slot() * 256 + (int)threadIdx.x;
+    const int ts = e / fmax, kk = e - ts * fmax;
+    if (ts >= ntiles) return;
+    const int2 tm = tmap[ts];
+    if (tm.x < 0) return;
+    const InstDesc &d = descs[tm.x];
+    if (k >= d.count || d.tiles[mu] == 1) return;
+    const int F = d.face_len[mu];
+    if (kk >= F) return;
+    const int t = tm.y;
+    const int32_t a = ((const GLOBAL int32_t *)d.face)[d.face_off[mu] + (int64_t)t * 2 * F + kk];
+    if (a < 0) return;
+    int c[3] = {t % d.tiles[0], (t / d.tiles[0]) % d.tiles[1], (DIM == 3) ? t / (d.tiles[0] * d.tiles[1]) : 0};
+    c[mu] = (c[mu] + 1 == d.tiles[mu]) ? 0 : c[mu] + 1;
+    const int nb = c[0] + d.tiles[0] * (c[1] + d.tiles[1] * c[2]);
+    const int32_t b = ((const GLOBAL int32_t *)d.face)[d.face_off[mu] + (int64_t)nb * 2 * F + F + kk];
+    gunion(d.label, (uint32_t)a, (uint32_t)b);
+}
+
+// ---------------------------------------------------------------------------
+// Reduction of the per-tile measurement partials into one record row, in a
+// fixed order (deterministic, also for the XY sums).  Workgroup t of a
+// lattice reduces slots t, t + ntiles, ... (XY: workgroup 0 all three and
+// rotates the projected sums back by phi).
+// ---------------------------------------------------------------------------
+template <int MODEL>
+__device__ void reduce_partials(const InstDesc &d, int t, uint32_t n, int64_t row)
 {
     __shared__ double s_red[4][3];
     __shared__ double s_phi;
-    const int2 tm = tmap[blockIdx.x];
-    if (tm.x < 0) return;
-    const InstDesc &d = descs[tm.x];
-    if (k >= d.count) return;
-    const int mu = blockIdx.y;
-    const int t = tm.y;
-    const int tid = threadIdx.x;
-    if (mu < DIM) {
-        if (mode != 0 || d.tiles[mu] == 1) return;
-        int c[3] = {t % d.tiles[0], (t / d.tiles[0]) % d.tiles[1], (DIM == 3) ? t / (d.tiles[0] * d.tiles[1]) : 0};
-        c[mu] = (c[mu] + 1 == d.tiles[mu]) ? 0 : c[mu] + 1;
-        const int nb = c[0] + d.tiles[0] * (c[1] + d.tiles[1] * c[2]);
-        const int F = d.face_len[mu];
-        const int32_t *fo = d.face + d.face_off[mu] + (int64_t)t * 2 * F;
-        const int32_t *fi = d.face + d.face_off[mu] + (int64_t)nb * 2 * F + F;
-        for (int kk = tid; kk < F; kk += 256) {
-            const int32_t a = fo[kk];
-            if (a < 0) continue;
-            gunion(d.label, (uint32_t)a, (uint32_t)fi[kk]);
-        }
-        return;
-    }
-    // reduction slice
-    if (mode == 0 && !d.measure) return;
-    int64_t row;
-    if (mode == 1) {
-        row = d.rec_cap;
-    } else {
-        if (d.rec_row0 < 0) return;
-        row = d.rec_row0 + (int64_t)k;
-        if (row >= d.rec_cap) return;
-    }
-    int64_t *rec = d.rec + row * d.nslots;
-    const int wv = tid >> 6, ln = tid & 63;
+    const int tid = threadIdx.x, wv = tid >> 6, ln = tid & 63;
+    GLOBAL int64_t *rec = (GLOBAL int64_t *)d.rec + row * d.nslots;
+    const GLOBAL int64_t *part = (const GLOBAL int64_t *)d.part;
     if (MODEL == XY) {
         if (t != 0) return;
-        if (tid == 0) s_phi = xy_phi(d, d.sweep0 + k);
+        if (tid == 0) s_phi = xy_phi(d, n);
         double acc[3] = {0.0, 0.0, 0.0};
         for (int tt = tid; tt < d.ntiles; tt += 256)
-            for (int c = 0; c < 3; ++c) acc[c] += __longlong_as_double(d.part[(int64_t)tt * 3 + c]);
+            for (int c = 0; c < 3; ++c) acc[c] += __longlong_as_double(part[(int64_t)tt * 3 + c]);
         for (int c = 0; c < 3; ++c) {
             const double v = wave_sum_d(acc[c]);
             if (ln == 0) s_red[wv][c] = v;
@@ -750,17 +917,16 @@ __global__ void __launch_bounds__(256) k_merge(const InstDesc *__restrict__ desc
             double sp, cp;
             sincos(s_phi, &sp, &cp);
             // sum of (cos, sin)(theta - phi) rotated back by phi
-            const double mx = cp * v[1] - sp * v[2];
-            const double my = sp * v[1] + cp * v[2];
             rec[0] = __double_as_longlong(v[0]);
-            rec[1] = __double_as_longlong(mx);
-            rec[2] = __double_as_longlong(my);
+            rec[1] = __double_as_longlong(cp * v[1] - sp * v[2]);
+            rec[2] = __double_as_longlong(sp * v[1] + cp * v[2]);
         }
+        __syncthreads();
         return;
     }
     for (int slot = t; slot < d.nslots; slot += d.ntiles) {
         long long acc = 0;
-        for (int tt = tid; tt < d.ntiles; tt += 256) acc += d.part[(int64_t)tt * d.nslots + slot];
+        for (int tt = tid; tt < d.ntiles; tt += 256) acc += part[(int64_t)tt * d.nslots + slot];
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
         if (ln == 0) s_red[wv][0] = __longlong_as_double(acc);
@@ -771,6 +937,17 @@ __global__ void __launch_bounds__(256) k_merge(const InstDesc *__restrict__ desc
         }
         __syncthreads();
     }
+}
+
+// Measurement of the current configuration alone: reduce into the scratch row.
+template <int MODEL>
+__global__ void __launch_bounds__(256) k_reduce(const InstDesc *__restrict__ descs, const int2 *__restrict__ tmap)
+{
+    const int2 tm = tmap[blockIdx.x];
+    if (tm.x < 0) return;
+    const InstDesc &d = descs[tm.x];
+    if (tm.y >= d.nslots && !(MODEL == XY && tm.y == 0)) return;
+    reduce_partials<MODEL>(d, tm.y, d.sweep0, d.rec_cap);
 }
 
 // ---------------------------------------------------------------------------
@@ -785,7 +962,7 @@ __global__ void __launch_bounds__(256) k_flip(const InstDesc *__restrict__ descs
     constexpr int NQ = T / 4;
     constexpr int QPT = (NQ + 255) / 256;
     __shared__ double s_phi;
-    const int2 tm = tmap[blockIdx.x];
+    const int2 tm = tmap[tile_slot()];
     if (tm.x < 0) return;
     const InstDesc &d = descs[tm.x];
     if (k >= d.count) return;
@@ -798,6 +975,10 @@ __global__ void __launch_bounds__(256) k_flip(const InstDesc *__restrict__ descs
     const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
     const int ex = min(TX, L - x0), ey = min(TY, L - y0), ez = (DIM == 3) ? min(TZ, L - z0) : 1;
     const int tid = threadIdx.x;
+    // the first workgroups of a lattice also reduce the sweep's measurement
+    if (d.measure && d.rec_row0 >= 0 && d.rec_row0 + (int64_t)k < d.rec_cap &&
+        (t < d.nslots || (MODEL == XY && t == 0)))
+        reduce_partials<MODEL>(d, t, n, d.rec_row0 + (int64_t)k);
     if (MODEL == XY) {
         if (tid == 0) s_phi = xy_phi(d, n);
         __syncthreads();
@@ -981,21 +1162,28 @@ hipError_t launch_bond(int model, int dim, int v, const InstDesc *dd, const int2
     return dim == 2 ? bond_dispatch<XY, 2>(v, dd, tm, nt, k, mode, s) : bond_dispatch<XY, 3>(v, dd, tm, nt, k, mode, s);
 }
 
-hipError_t launch_merge(int dim, const InstDesc *dd, const int2 *tm, int nt, uint32_t k, int mode, int model,
-                        int, hipStream_t s)
+hipError_t launch_merge(int dim, int model, int v, const InstDesc *dd, const int2 *tm, int nt, uint32_t k,
+                        hipStream_t s)
 {
     if (nt <= 0) return hipSuccess;
-    const dim3 grid(nt, dim + 1);
-    if (model == ISING) {
-        if (dim == 2) hipLaunchKernelGGL((k_merge<ISING, 2>), grid, dim3(256), 0, s, dd, tm, k, mode);
-        else hipLaunchKernelGGL((k_merge<ISING, 3>), grid, dim3(256), 0, s, dd, tm, k, mode);
-    } else if (model == POTTS) {
-        if (dim == 2) hipLaunchKernelGGL((k_merge<POTTS, 2>), grid, dim3(256), 0, s, dd, tm, k, mode);
-        else hipLaunchKernelGGL((k_merge<POTTS, 3>), grid, dim3(256), 0, s, dd, tm, k, mode);
-    } else {
-        if (dim == 2) hipLaunchKernelGGL((k_merge<XY, 2>), grid, dim3(256), 0, s, dd, tm, k, mode);
-        else hipLaunchKernelGGL((k_merge<XY, 3>), grid, dim3(256), 0, s, dd, tm, k, mode);
-    }
+    const TileShape ts = tile_shape(model, dim, v);
+    const int ext[3] = {ts.tx, ts.ty, dim == 3 ? ts.tz : 1};
+    const int T = ext[0] * ext[1] * ext[2];
+    int fmax = 0;
+    for (int mu = 0; mu < dim; ++mu) fmax = T / ext[mu] > fmax ? T / ext[mu] : fmax;
+    const long long blocks = ((long long)nt * fmax + 255) / 256;
+    const dim3 grid((unsigned)blocks, dim);
+    if (dim == 2) hipLaunchKernelGGL((k_merge<2>), grid, dim3(256), 0, s, dd, tm, nt, fmax, k);
+    else hipLaunchKernelGGL((k_merge<3>), grid, dim3(256), 0, s, dd, tm, nt, fmax, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce(int model, const InstDesc *dd, const int2 *tm, int nt, hipStream_t s)
+{
+    if (nt <= 0) return hipSuccess;
+    if (model == ISING) hipLaunchKernelGGL((k_reduce<ISING>), dim3(nt), dim3(256), 0, s, dd, tm);
+    else if (model == POTTS) hipLaunchKernelGGL((k_reduce<POTTS>), dim3(nt), dim3(256), 0, s, dd, tm);
+    else hipLaunchKernelGGL((k_reduce<XY>), dim3(nt), dim3(256), 0, s, dd, tm);
     return hipGetLastError();
 }
 

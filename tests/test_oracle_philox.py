@@ -64,7 +64,7 @@ def test_word_layout():
 
 def test_philox_uniformity():
     # chi^2 of the top byte and balance of every bit over 2^16 consecutive words
-    words = np.array([oracle.word(1, 0, oracle.TAG_BOND_X, 0, w) for w in range(1 << 16)],
+    words = np.array([oracle.word(1, 0, oracle.TAG_BOND, 0, w) for w in range(1 << 16)],
                      dtype=np.uint64)
     counts = np.bincount((words >> 24).astype(np.int64), minlength=256)
     exp = len(words) / 256
@@ -74,3 +74,35 @@ def test_philox_uniformity():
     for bit in range(32):
         ones = int(((words >> bit) & 1).sum())
         assert abs(ones - len(words) / 2) < 6 * np.sqrt(len(words) / 4)
+
+
+def test_bond_uniform_layout():
+    # U(i, mu) = P << 16 | S: primaries packed two per BOND word (x high, y low),
+    # z primaries two per BOND_Z word, secondaries from the tie stream
+    seed, rep, n = 0x5EED, 2, 7
+    for dim in (2, 3):
+        for i in (0, 1, 2, 3, 4, 5, 1001, 2**20 + 3):
+            for mu in range(dim):
+                u = oracle.bond_uniform(seed, rep, n, dim, i, mu)
+                if mu < 2:
+                    w = oracle.word(seed, rep, oracle.TAG_BOND, n, i)
+                    p = (w >> 16) if mu == 0 else (w & 0xFFFF)
+                else:
+                    w = oracle.word(seed, rep, oracle.TAG_BOND_Z, n, i >> 1)
+                    p = (w & 0xFFFF) if (i & 1) else (w >> 16)
+                s = oracle.word(seed, rep, oracle.TAG_BOND_TIE, n, dim * i + mu) >> 16
+                assert u == (p << 16) | s
+
+
+def test_bond_uniform_is_uniform():
+    u = np.array([oracle.bond_uniform(9, 0, 3, 3, i, mu) for i in range(20000) for mu in range(3)],
+                 dtype=np.uint64)
+    for shift in (28, 12):  # a primary nibble and a secondary nibble
+        counts = np.bincount(((u >> shift) & 15).astype(np.int64), minlength=16)
+        exp = len(u) / 16
+        chi2 = float(((counts - exp) ** 2 / exp).sum())
+        assert chi2 < 60  # 15 dof
+    d = np.array([oracle.cluster_decision(0, 2, 9, 0, 3, g) for g in range(20000)])
+    assert abs(d.mean() - 0.5) < 0.02
+    d = np.array([oracle.cluster_decision(1, 5, 9, 0, 3, g) for g in range(20000)])
+    assert np.all(np.bincount(d, minlength=5) > 3600)

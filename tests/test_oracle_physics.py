@@ -21,6 +21,7 @@ import pytest
 from scipy.special import ellipk
 
 import oracle
+from exact_ising2d import energy_per_site
 from test_oracle_enumeration import batch_mean_z
 
 
@@ -41,11 +42,36 @@ def test_onsager_energy(T):
     s0 = oracle.init_state(oracle.ISING, 2, L, 2, seed=21)
     r = oracle.sweeps(oracle.ISING, 2, L, 2, beta, 21, 0, 0, 2200, s0, last=False)["records"]
     e = r["energy"][200:] / N
+    # at L = 64 and these temperatures the finite-size correction is < 1e-9
+    assert abs(energy_per_site(beta, L) - onsager_u(beta)) < 1e-8
     assert abs(batch_mean_z(e, onsager_u(beta), nb=20)) < 5
-    assert abs(e.mean() - onsager_u(beta)) < 2e-3
+    assert abs(e.mean() - onsager_u(beta)) < 5e-3
     if T < 2.269:
         m = np.abs(r["mx"][200:]) / N
-        assert abs(m.mean() - yang_m(beta)) < 3e-3
+        assert abs(m.mean() - yang_m(beta)) < 5e-3
+
+
+def test_kaufman_matches_enumeration():
+    from test_oracle_enumeration import exact_from_samples, ising2d_enum
+    E, _ = ising2d_enum(4)
+    for beta in (0.3, math.log(1 + math.sqrt(2)) / 2, 0.5):
+        ex, _, _ = exact_from_samples(E, {"e": E / 16}, beta)
+        assert energy_per_site(beta, 4) == pytest.approx(ex["e"], abs=1e-8)
+
+
+@pytest.mark.parametrize("L,T", [(16, 2.0), (16, 2.0 / math.log(1 + math.sqrt(2))), (12, 3.0)])
+def test_kaufman_finite_lattice(L, T):
+    """The chain's energy against the exact finite-L value (no finite-size
+    approximation), at high statistics."""
+    beta = 1.0 / T
+    N = L * L
+    zs = []
+    for seed in (1, 2):
+        s0 = oracle.init_state(oracle.ISING, 2, L, 2, seed)
+        r = oracle.sweeps(oracle.ISING, 2, L, 2, beta, seed, 0, 0, 60000, s0, last=False)["records"]
+        zs.append(batch_mean_z(r["energy"][1000:] / N, energy_per_site(beta, L), nb=50))
+    assert all(abs(z) < 5 for z in zs), zs
+    assert abs(sum(zs) / math.sqrt(len(zs))) < 5
 
 
 def test_critical_threshold():
@@ -118,7 +144,7 @@ def test_xy_reflection_geometry():
     for sweep in range(3):
         phi = oracle.xy_phi(8, 0, sweep)
         new = oracle.set_clusters(oracle.XY, dim, L, 0, 8, 0, sweep, labels, th)
-        flip = np.array([oracle.word(8, 0, oracle.TAG_CLUSTER, sweep, i) >> 31 for i in range(N)])
+        flip = np.array([oracle.cluster_decision(oracle.XY, 0, 8, 0, sweep, i) for i in range(N)])
         assert 0.35 < flip.mean() < 0.65
         assert np.all((new >= 0) & (new < np.float32(2 * math.pi)))
         np.testing.assert_array_equal(new[flip == 0], th[flip == 0])
