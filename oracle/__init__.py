@@ -45,9 +45,9 @@ def lib():
         L.swo_philox4x32_10.argtypes = [vp, vp, vp]
         L.swo_word.argtypes = [u64, u32, u32, u32, u64]
         L.swo_word.restype = u32
-        L.swo_bond_uniform.argtypes = [u64, u32, u32, i32, u64, i32]
+        L.swo_bond_uniform.argtypes = [u64, u32, u32, i32, i32, u64, i32]
         L.swo_bond_uniform.restype = u32
-        L.swo_cluster_decision.argtypes = [i32, i32, u64, u32, u32, u64]
+        L.swo_cluster_decision.argtypes = [i32, i32, u64, u32, u32, i32, i32, u64]
         L.swo_cluster_decision.restype = u32
         L.swo_threshold.argtypes = [i32, dbl]
         L.swo_threshold.restype = u64
@@ -83,12 +83,12 @@ def word(seed, rep, tag, sweep, w):
     return int(lib().swo_word(seed, rep, tag, sweep, w))
 
 
-def bond_uniform(seed, rep, sweep, dim, i, mu):
-    return int(lib().swo_bond_uniform(seed, rep, sweep, dim, i, mu))
+def bond_uniform(seed, rep, sweep, dim, L, g, mu):
+    return int(lib().swo_bond_uniform(seed, rep, sweep, dim, L, g, mu))
 
 
-def cluster_decision(model, q, seed, rep, sweep, g):
-    return int(lib().swo_cluster_decision(model, q, seed, rep, sweep, g))
+def cluster_decision(model, q, seed, rep, sweep, dim, L, g):
+    return int(lib().swo_cluster_decision(model, q, seed, rep, sweep, dim, L, g))
 
 
 def threshold(model, beta):

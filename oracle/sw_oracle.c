@@ -34,13 +34,19 @@
  *       seed s is output lane (w mod 4) of Philox(counter = (w div 4, n, tag,
  *       r), key = (s mod 2^32, s div 2^32)).  n is the 0-based sweep index,
  *       cumulative over calls.  Tags: BOND 0, BOND_Z 1, BOND_TIE 2,
- *       CLUSTER 3, GLOBAL 4, INIT 5.  The uniform of bond (i, mu) is the
- *       32-bit number U = P * 2^16 + S: the primary P is the high (x) or low
- *       (y) half of word i of BOND, or for z the high (i even) or low (i
- *       odd) half of word i/2 of BOND_Z; the secondary S is the high half of
- *       word d*i + mu of BOND_TIE.  Cluster decisions: Ising, XY and Potts
- *       with q = 2 take bit (g mod 32) of word g/32 of CLUSTER for the
- *       cluster labelled g; Potts with q >= 3 takes word g of CLUSTER.
+ *       CLUSTER 3, GLOBAL 4, INIT 5.  Site (x, y, z) of an L^d lattice has
+ *       row-major index g = x + L (y + L z).  Bond and Potts words are laid
+ *       out by columns: the Philox block with counter word
+ *       b = x + L (floor(y/4) + ceil(L/4) z) holds, in lanes 0..3, the words
+ *       of the sites (x, 4 floor(y/4) + 0..3, z).  The uniform of bond
+ *       (g, mu) is the 32-bit number U = P * 2^16 + S: the primary P is the
+ *       high (x) or low (y) half of that BOND word; for z it is the high (y
+ *       even) or low (y odd) half of lane floor((y mod 8)/2) of the BOND_Z
+ *       block b = x + L (floor(y/8) + ceil(L/8) z); the secondary S is the
+ *       high half of word d*g + mu of BOND_TIE.  Cluster decisions: Ising,
+ *       XY and Potts with q = 2 take bit (g mod 32) of word g/32 of CLUSTER
+ *       for the cluster labelled g; Potts with q >= 3 takes the CLUSTER word
+ *       of site g in the column layout of the bond words.
  *   R8  a bond is active iff the pair is aligned and u < p with strict <;
  *       u = word * 2^-32, compared exactly as the integer test word < thr
  *       with thr = floor(p * 2^32).
@@ -92,25 +98,42 @@ uint32_t swo_word(uint64_t seed, uint32_t rep, uint32_t tag, uint32_t sweep, uin
     return out[w & 3u];
 }
 
-uint32_t swo_bond_uniform(uint64_t seed, uint32_t rep, uint32_t sweep, int dim, uint64_t i, int mu)
+/* Word of site (x, y, z) in the column layout of R7: lane (y mod 4) of the
+ * block x + L (floor(y/4) + ceil(L/4) z) of stream (tag, sweep). */
+static uint32_t column_word(uint64_t seed, uint32_t rep, uint32_t tag, uint32_t sweep, int L,
+                            uint64_t x, uint64_t y, uint64_t z)
 {
+    uint64_t q4 = ((uint64_t)L + 3) / 4;
+    uint64_t block = x + (uint64_t)L * (y / 4 + q4 * z);
+    return swo_word(seed, rep, tag, sweep, 4 * block + (y % 4));
+}
+
+uint32_t swo_bond_uniform(uint64_t seed, uint32_t rep, uint32_t sweep, int dim, int L, uint64_t g,
+                          int mu)
+{
+    uint64_t x = g % (uint64_t)L, y = (g / (uint64_t)L) % (uint64_t)L;
+    uint64_t z = (dim == 3) ? g / ((uint64_t)L * (uint64_t)L) : 0;
     uint32_t p;
     if (mu < 2) {
-        uint32_t w = swo_word(seed, rep, SWO_TAG_BOND, sweep, i);
+        uint32_t w = column_word(seed, rep, SWO_TAG_BOND, sweep, L, x, y, z);
         p = (mu == 0) ? (w >> 16) : (w & 0xffffu);
     } else {
-        uint32_t w = swo_word(seed, rep, SWO_TAG_BOND_Z, sweep, i >> 1);
-        p = (i & 1) ? (w & 0xffffu) : (w >> 16);
+        uint64_t q8 = ((uint64_t)L + 7) / 8;
+        uint64_t block = x + (uint64_t)L * (y / 8 + q8 * z);
+        uint32_t w = swo_word(seed, rep, SWO_TAG_BOND_Z, sweep, 4 * block + (y % 8) / 2);
+        p = (y % 2) ? (w & 0xffffu) : (w >> 16);
     }
-    uint32_t s = swo_word(seed, rep, SWO_TAG_BOND_TIE, sweep, (uint64_t)dim * i + (uint64_t)mu) >> 16;
+    uint32_t s = swo_word(seed, rep, SWO_TAG_BOND_TIE, sweep, (uint64_t)dim * g + (uint64_t)mu) >> 16;
     return (p << 16) | s;
 }
 
 uint32_t swo_cluster_decision(int model, int q, uint64_t seed, uint32_t rep, uint32_t sweep,
-                              uint64_t g)
+                              int dim, int L, uint64_t g)
 {
     if (model == SWO_POTTS && q > 2) {
-        uint32_t w = swo_word(seed, rep, SWO_TAG_CLUSTER, sweep, g);
+        uint64_t x = g % (uint64_t)L, y = (g / (uint64_t)L) % (uint64_t)L;
+        uint64_t z = (dim == 3) ? g / ((uint64_t)L * (uint64_t)L) : 0;
+        uint32_t w = column_word(seed, rep, SWO_TAG_CLUSTER, sweep, L, x, y, z);
         return (uint32_t)(((uint64_t)w * (uint64_t)q) >> 32);
     }
     uint32_t w = swo_word(seed, rep, SWO_TAG_CLUSTER, sweep, g >> 5);
@@ -218,7 +241,7 @@ int64_t swo_bonds(int model, int dim, int L, int q, double beta, uint64_t seed, 
         uint8_t b = 0;
         for (int mu = 0; mu < dim; ++mu) {
             int64_t j = neighbour(dim, L, i, mu);
-            uint32_t w = swo_bond_uniform(seed, rep, sweep, dim, (uint64_t)i, mu);
+            uint32_t w = swo_bond_uniform(seed, rep, sweep, dim, L, (uint64_t)i, mu);
             int on;
             if (model == SWO_ISING) {
                 const int8_t *s = (const int8_t *)state;
@@ -339,7 +362,7 @@ void swo_set_clusters(int model, int dim, int L, int q, uint64_t seed, uint32_t 
     int64_t N = num_sites(dim, L);
     double phi = (model == SWO_XY) ? swo_xy_phi(seed, rep, sweep) : 0.0;
     for (int64_t i = 0; i < N; ++i) {
-        uint32_t dec = swo_cluster_decision(model, q, seed, rep, sweep, (uint64_t)labels[i]);
+        uint32_t dec = swo_cluster_decision(model, q, seed, rep, sweep, dim, L, (uint64_t)labels[i]);
         if (model == SWO_ISING) {
             ((int8_t *)state)[i] = dec ? (int8_t)-1 : (int8_t)1;
         } else if (model == SWO_POTTS) {

@@ -37,14 +37,16 @@ void swo_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
 /* Word w of the random stream (tag, sweep) of replica `rep` under `seed`. */
 uint32_t swo_word(uint64_t seed, uint32_t rep, uint32_t tag, uint32_t sweep, uint64_t w);
 
-/* The 32-bit uniform of bond (i, mu) at sweep n: (P << 16) | S with the
- * 16-bit primary P and the 16-bit secondary S (see sw_oracle.c, R7). */
-uint32_t swo_bond_uniform(uint64_t seed, uint32_t rep, uint32_t sweep, int dim, uint64_t i, int mu);
+/* The 32-bit uniform of bond (g, mu) of an L^dim lattice at sweep n:
+ * (P << 16) | S with the 16-bit primary P and the 16-bit secondary S (see
+ * sw_oracle.c, R7). */
+uint32_t swo_bond_uniform(uint64_t seed, uint32_t rep, uint32_t sweep, int dim, int L, uint64_t g,
+                          int mu);
 
 /* Random decision of the cluster whose label is g: Ising/XY/Potts(q=2) use
  * one bit, Potts q >= 3 a new state in [0,q). */
 uint32_t swo_cluster_decision(int model, int q, uint64_t seed, uint32_t rep, uint32_t sweep,
-                              uint64_t g);
+                              int dim, int L, uint64_t g);
 
 /* Bond threshold for Ising (model 0) and Potts (model 1): floor(p * 2^32). */
 uint64_t swo_threshold(int model, double beta);

@@ -77,32 +77,70 @@ def test_philox_uniformity():
 
 
 def test_bond_uniform_layout():
-    # U(i, mu) = P << 16 | S: primaries packed two per BOND word (x high, y low),
-    # z primaries two per BOND_Z word, secondaries from the tie stream
+    # U(g, mu) = P << 16 | S.  Bond primaries are laid out by columns: the
+    # Philox block x + L (y//4 + ceil(L/4) z) of BOND holds the words of sites
+    # (x, 4 (y//4) + 0..3, z), x primary high, y primary low; z primaries come
+    # two per word from BOND_Z blocks of eight rows; secondaries from the tie
+    # stream at the row-major bond index
     seed, rep, n = 0x5EED, 2, 7
-    for dim in (2, 3):
-        for i in (0, 1, 2, 3, 4, 5, 1001, 2**20 + 3):
+    key = [seed & 0xFFFFFFFF, seed >> 32]
+    for dim, L in ((2, 6), (2, 13), (3, 5), (3, 11)):
+        N = L ** dim
+        for g in sorted({0, 1, 2, 3, 4, 5, L, L + 1, 3 * L - 1, N // 2, N - 1}):
+            x, y, z = g % L, (g // L) % L, g // (L * L)
+            blk = oracle.philox([x + L * (y // 4 + -(-L // 4) * z), n, oracle.TAG_BOND, rep], key)
+            w = int(blk[y % 4])
             for mu in range(dim):
-                u = oracle.bond_uniform(seed, rep, n, dim, i, mu)
+                u = oracle.bond_uniform(seed, rep, n, dim, L, g, mu)
                 if mu < 2:
-                    w = oracle.word(seed, rep, oracle.TAG_BOND, n, i)
                     p = (w >> 16) if mu == 0 else (w & 0xFFFF)
                 else:
-                    w = oracle.word(seed, rep, oracle.TAG_BOND_Z, n, i >> 1)
-                    p = (w & 0xFFFF) if (i & 1) else (w >> 16)
-                s = oracle.word(seed, rep, oracle.TAG_BOND_TIE, n, dim * i + mu) >> 16
-                assert u == (p << 16) | s
+                    zb = oracle.philox([x + L * (y // 8 + -(-L // 8) * z), n, oracle.TAG_BOND_Z, rep], key)
+                    wz = int(zb[(y % 8) // 2])
+                    p = (wz & 0xFFFF) if (y & 1) else (wz >> 16)
+                s_ = oracle.word(seed, rep, oracle.TAG_BOND_TIE, n, dim * g + mu) >> 16
+                assert u == (p << 16) | s_, (dim, L, g, mu)
+
+
+def test_column_layout_is_a_bijection():
+    # every BOND word (and BOND_Z half) is used by exactly one site, so no two
+    # bonds share a primary
+    for dim, L in ((2, 10), (3, 6)):
+        seen = {}
+        for g in range(L ** dim):
+            x, y, z = g % L, (g // L) % L, g // (L * L)
+            k = (x + L * (y // 4 + -(-L // 4) * z), y % 4)
+            assert k not in seen
+            seen[k] = g
+            if dim == 3:
+                kz = ("z", x + L * (y // 8 + -(-L // 8) * z), y % 8)
+                assert kz not in seen
+                seen[kz] = g
 
 
 def test_bond_uniform_is_uniform():
-    u = np.array([oracle.bond_uniform(9, 0, 3, 3, i, mu) for i in range(20000) for mu in range(3)],
+    L = 28
+    u = np.array([oracle.bond_uniform(9, 0, 3, 3, L, i, mu) for i in range(L ** 3) for mu in range(3)],
                  dtype=np.uint64)
     for shift in (28, 12):  # a primary nibble and a secondary nibble
         counts = np.bincount(((u >> shift) & 15).astype(np.int64), minlength=16)
         exp = len(u) / 16
         chi2 = float(((counts - exp) ** 2 / exp).sum())
         assert chi2 < 60  # 15 dof
-    d = np.array([oracle.cluster_decision(0, 2, 9, 0, 3, g) for g in range(20000)])
+    d = np.array([oracle.cluster_decision(0, 2, 9, 0, 3, 2, 200, g) for g in range(20000)])
     assert abs(d.mean() - 0.5) < 0.02
-    d = np.array([oracle.cluster_decision(1, 5, 9, 0, 3, g) for g in range(20000)])
+    d = np.array([oracle.cluster_decision(1, 5, 9, 0, 3, 2, 200, g) for g in range(20000)])
     assert np.all(np.bincount(d, minlength=5) > 3600)
+
+
+def test_potts_decision_layout():
+    # Potts q >= 3: the new state of the cluster rooted at g is floor(w q / 2^32)
+    # for the CLUSTER word of site g in the column layout
+    seed, rep, n, q = 77, 1, 4, 7
+    key = [seed & 0xFFFFFFFF, seed >> 32]
+    for dim, L in ((2, 9), (3, 7)):
+        for g in (0, 5, L + 3, L ** dim - 1):
+            x, y, z = g % L, (g // L) % L, g // (L * L)
+            blk = oracle.philox([x + L * (y // 4 + -(-L // 4) * z), n, oracle.TAG_CLUSTER, rep], key)
+            want = (int(blk[y % 4]) * q) >> 32
+            assert oracle.cluster_decision(oracle.POTTS, q, seed, rep, n, dim, L, g) == want

@@ -144,7 +144,7 @@ def test_xy_reflection_geometry():
     for sweep in range(3):
         phi = oracle.xy_phi(8, 0, sweep)
         new = oracle.set_clusters(oracle.XY, dim, L, 0, 8, 0, sweep, labels, th)
-        flip = np.array([oracle.cluster_decision(oracle.XY, 0, 8, 0, sweep, i) for i in range(N)])
+        flip = np.array([oracle.cluster_decision(oracle.XY, 0, 8, 0, sweep, dim, L, i) for i in range(N)])
         assert 0.35 < flip.mean() < 0.65
         assert np.all((new >= 0) & (new < np.float32(2 * math.pi)))
         np.testing.assert_array_equal(new[flip == 0], th[flip == 0])
