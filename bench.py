@@ -7,7 +7,12 @@ tile labelling, label merge, cluster flip, per-sweep measurement).  Prints one
 JSON line with spin updates/ns, the HBM roofline of the dominant kernel and
 the oracle timed on the host as a CPU baseline.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config C2|C1|C3|C4]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config C2|C1|C3|C4|C5]
+
+C5 is the served form: a seeded Poisson job mix (--jobs, --rate) replayed in
+wall-clock time against the continuous-batching server, reporting served
+throughput, p50/p99 job latency (arrival to last sweep) and the same jobs
+run back to back in the plain form.
 """
 import argparse
 import hashlib
@@ -27,12 +32,15 @@ WORKLOADS = {
     "C2": ["C2-potts", "C2-ising"],
     "C3": ["C3"],
     "C4": ["C4"],
+    "C5": [],
 }
 DESCRIPTION = {
     "C1": "2D Ising L=64 T=2.269185 seed 1, plain form",
     "C2": "2D q=3 Potts + 2D Ising, L=4096, exact Tc, plain form (one lattice per launch)",
     "C3": "3D Ising L=256 T=4.5115, plain form",
     "C4": "3D XY L=128, 32 replicas over [0.95 Tc, 1.05 Tc], batched form",
+    "C5": "served job mix (2D Ising, 2D Potts q in {3,4,10}, 3D Ising, 3D XY; L log-uniform; "
+          "100-5000 sweeps), Poisson arrivals, continuous batching",
 }
 
 
@@ -81,6 +89,63 @@ def cpu_baseline(config, lattices):
             "sample": f"{sweeps} sweep(s) from hot start of each of: {names}; {dt:.1f} s"}
 
 
+def served(n_jobs, rate, seed=2014):
+    """Replay the job mix against the server; then the same jobs in the plain
+    form, one after another."""
+    import numpy as np
+    import paper_1403_7560_amd as sw
+    from paper_1403_7560_amd import inputs
+    jobs = inputs.job_mix(n_jobs, rate=rate, seed=seed)
+    updates = sum(j["L"] ** j["dim"] * j["sweeps"] for j in jobs)
+    srv = sw.Server(96 << 30, max_active=128, chunk=32)
+    lat_s = np.zeros(n_jobs)
+    finish = np.zeros(n_jobs)
+    info = {}
+    pending = set()
+    i = 0
+    t0 = time.perf_counter()
+    while len(info) < n_jobs or pending:
+        now = time.perf_counter() - t0
+        while i < n_jobs and jobs[i]["arrival"] <= now:
+            j = jobs[i]
+            jid = srv.submit(j["model"], j["dim"], j["L"], j["q"], j["beta"], j["seed"], 0, j["sweeps"])
+            info[jid] = (i, time.perf_counter() - t0 - j["arrival"])
+            pending.add(jid)
+            i += 1
+        left = srv.step()
+        for jid in list(pending):
+            r = srv.poll(jid)
+            if r is None:
+                continue
+            if r["status"] != 0:
+                raise RuntimeError(f"job {jid} failed with status {r['status']}")
+            k, delay = info[jid]
+            lat_s[k] = (r["finish_s"] - r["submit_s"]) + delay
+            finish[k] = time.perf_counter() - t0
+            pending.discard(jid)
+        if left == 0 and i < n_jobs:
+            time.sleep(max(0.0, jobs[i]["arrival"] - (time.perf_counter() - t0)))
+    makespan = finish.max() - jobs[0]["arrival"]
+    srv.close()
+    t1 = time.perf_counter()
+    for j in jobs:
+        lat = sw.Lattice(j["model"], j["dim"], j["L"], j["q"], j["beta"], j["seed"])
+        lat.sweep(j["sweeps"])
+        lat.close()
+    plain_s = time.perf_counter() - t1
+    value = updates / (makespan * 1e9)
+    plain = updates / (plain_s * 1e9)
+    return {
+        "value": value, "makespan_s": makespan, "updates": updates,
+        "latency_s": {"p50": round(float(np.percentile(lat_s, 50)), 4),
+                      "p99": round(float(np.percentile(lat_s, 99)), 4),
+                      "max": round(float(lat_s.max()), 4)},
+        "offered_load": round(updates / ((jobs[-1]["arrival"] - jobs[0]["arrival"]) * 1e9), 2),
+        "plain_form": {"value": round(plain, 3), "seconds": round(plain_s, 2)},
+        "speedup_vs_plain": round(value / plain, 3),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -88,6 +153,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--config", default="C2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--jobs", type=int, default=300, help="C5: jobs in the replayed trace")
+    ap.add_argument("--rate", type=float, default=200.0, help="C5: arrivals per second")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="also copy this many bytes device-to-device once (counter calibration)")
     args = ap.parse_args()
@@ -109,6 +176,24 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+
+    if args.config == "C5":
+        r = served(args.jobs, args.rate)
+        out = {
+            "metric": "spin updates/ns", "value": round(r["value"], 3), "unit": "spin updates/ns",
+            "n_gpus": 1, "steps": args.jobs, "warmup": 0,
+            "ms_per_step": round(r["makespan_s"] * 1e3 / args.jobs, 4),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+            "data": "synthetic",
+            "config": {"workload": f"C5: {DESCRIPTION['C5']}", "jobs": args.jobs, "rate_per_s": args.rate,
+                       "updates": r["updates"], "offered_load_updates_per_ns": r["offered_load"],
+                       "step": "one served job"},
+            "latency_s": r["latency_s"], "plain_form": r["plain_form"],
+            "speedup_vs_plain": r["speedup_vs_plain"],
+            "roofline": None, "cpu_baseline": None,
+        }
+        print(json.dumps(out), flush=True)
+        return
 
     lattices = []
     default_steps = None

@@ -92,6 +92,31 @@ sw_handle sw_create(int model, int dim, int L, int q, double beta, uint64_t seed
 sw_handle sw_create_replica(int model, int dim, int L, int q, double beta, uint64_t seed,
                             uint32_t replica);
 
+/* As sw_create_replica on an explicit tile shape: tile in [0, sw_tile_count)
+ * picks the shape of the labelling tiles (Sec. 2, step (2): the local pass
+ * works on one tile in on-chip memory), -1 the tuned or default shape.  The
+ * shape changes the speed, never the trajectory.  NULL on error. */
+sw_handle sw_create_tiled(int model, int dim, int L, int q, double beta, uint64_t seed,
+                          uint32_t replica, int tile);
+
+/* Number of tile shapes for (model, dim), and the extent (tx, ty, tz) of
+ * shape `tile` (tz = 1 in 2D).  Host-only; SW_E_INVALID on bad arguments. */
+int sw_tile_count(int model, int dim);
+int sw_tile_shape(int model, int dim, int tile, int *tx, int *ty, int *tz);
+
+/* Tile shape index of a handle. */
+int sw_get_tile(sw_handle h);
+
+/* Tuner: for every tile shape, create a scratch lattice (model, dim, L, q,
+ * beta), run 2 warm-up and `sweeps` timed sweeps (1 .. 100000, HIP events)
+ * and record the fastest shape for (model, dim, L) in a process-wide table
+ * that later sw_create / sw_create_replica / batch / server lattices of that
+ * (model, dim, L) use.  *best receives the shape, ms_per_sweep (if not NULL,
+ * sw_tile_count entries) each shape's time.  Synchronous; allocates and frees
+ * the scratch lattices.  Thread-safe table; SW_E_* on error. */
+int sw_tune(int model, int dim, int L, int q, double beta, int sweeps, int *best,
+            double *ms_per_sweep);
+
 /* Run n >= 0 sweeps.  Before each sweep the configuration is measured into
  * the record series (when measuring is on, the default).  Synchronous. */
 int sw_sweep(sw_handle h, int64_t n);

@@ -57,6 +57,11 @@ vp, i32, i64, u32, u64, dbl = (ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ct
 SIGNATURES = {
     "sw_create": (vp, [i32, i32, i32, i32, dbl, u64]),
     "sw_create_replica": (vp, [i32, i32, i32, i32, dbl, u64, u32]),
+    "sw_create_tiled": (vp, [i32, i32, i32, i32, dbl, u64, u32, i32]),
+    "sw_tile_count": (i32, [i32, i32]),
+    "sw_tile_shape": (i32, [i32, i32, i32, vp, vp, vp]),
+    "sw_get_tile": (i32, [vp]),
+    "sw_tune": (i32, [i32, i32, i32, i32, dbl, i32, vp, vp]),
     "sw_sweep": (i32, [vp, i64]),
     "sw_measure": (i32, [vp, vp, vp, vp, vp]),
     "sw_reset_measure": (i32, [vp]),
@@ -128,13 +133,16 @@ def nsites(dim, L):
 class Lattice:
     """One lattice (plain form).  Mirrors sw_create_replica / sw_* calls."""
 
-    def __init__(self, model, dim, L, q=2, beta=0.0, seed=0, replica=0, _handle=None):
+    def __init__(self, model, dim, L, q=2, beta=0.0, seed=0, replica=0, tile=None, _handle=None):
         self.model, self.dim, self.L = model, dim, L
         self.q = 2 if model == ISING else (0 if model == XY else q)
         self.N = L ** dim
         self._owned = _handle is None
         if _handle is None:
-            h = lib().sw_create_replica(model, dim, L, self.q, float(beta), seed, replica)
+            if tile is None:
+                h = lib().sw_create_replica(model, dim, L, self.q, float(beta), seed, replica)
+            else:
+                h = lib().sw_create_tiled(model, dim, L, self.q, float(beta), seed, replica, int(tile))
             if not h:
                 raise SWError(-1, last_error())
             self.h = h
@@ -151,6 +159,11 @@ class Lattice:
             self.close()
         except Exception:
             pass
+
+    @property
+    def tile(self):
+        """Index of the tile shape this lattice runs with."""
+        return _check(lib().sw_get_tile(self.h))
 
     def sweep(self, n):
         _check(lib().sw_sweep(self.h, int(n)))
@@ -304,3 +317,25 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def tile_count(model, dim):
+    return _check(lib().sw_tile_count(model, dim))
+
+
+def tile_shape(model, dim, tile):
+    a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(lib().sw_tile_shape(model, dim, tile, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return a.value, b.value, c.value
+
+
+def tune(model, dim, L, q=2, beta=0.0, sweeps=20):
+    """Time every tile shape on a scratch lattice; the fastest becomes the
+    shape of lattices created afterwards for (model, dim, L).  Returns
+    (best, ms per sweep of each shape)."""
+    q = 2 if model == ISING else (0 if model == XY else q)
+    n = tile_count(model, dim)
+    best = ctypes.c_int()
+    ms = (ctypes.c_double * n)()
+    _check(lib().sw_tune(model, dim, L, q, float(beta), int(sweeps), ctypes.byref(best), ms))
+    return best.value, list(ms)

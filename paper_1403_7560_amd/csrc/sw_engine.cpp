@@ -14,6 +14,7 @@
 #include <deque>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -257,6 +258,9 @@ struct Lattice {
         for (int t = 0; t < ntiles; ++t) tm[t] = make_int2(0, t);
         HIPCHK(hipMemcpy(d_tmap, tm.data(), tm.size() * sizeof(int2), hipMemcpyHostToDevice));
         HIPCHK(hipMemsetAsync(bond, 0, (size_t)N, stream));
+        // face slots outside the lattice (ragged tiles) are never written and
+        // must read as "no bond" (-1)
+        HIPCHK(hipMemsetAsync(face, 0xFF, (size_t)std::max<int64_t>(face_total, 1) * 4, stream));
         // hot start
         InstDesc d = desc();
         HIPCHK(hipMemcpyAsync(d_solo, &d, sizeof(d), hipMemcpyHostToDevice, stream));
@@ -436,6 +440,22 @@ static hipStream_t make_stream()
     hipStream_t s = nullptr;
     if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return nullptr;
     return s;
+}
+
+// ---------------------------------------------------------------------------
+// Tile shapes chosen by the tuner, per (model, dim, L); lattices created
+// without an explicit shape take the tuned one, else shape 0.  The shape
+// never changes a trajectory (labels are canonical, random words are drawn
+// per site), only the speed.
+// ---------------------------------------------------------------------------
+static std::mutex g_tune_mu;
+static std::map<std::tuple<int, int, int>, int> g_tuned;
+
+static int tuned_tile(int model, int dim, int L)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(std::make_tuple(model, dim, L));
+    return it == g_tuned.end() ? 0 : it->second;
 }
 
 // ---------------------------------------------------------------------------
@@ -688,7 +708,8 @@ struct sw_server_s {
             queue.pop_front();
             sj->lat.reset(new Lattice());
             const sw_job_desc &jd = sj->job.lattice;
-            int rc = sj->lat->create(jd.model, jd.dim, jd.L, jd.q, jd.beta, jd.seed, jd.replica, 0, stream);
+            int rc = sj->lat->create(jd.model, jd.dim, jd.L, jd.q, jd.beta, jd.seed, jd.replica,
+                                     tuned_tile(jd.model, jd.dim, jd.L), stream);
             if (rc) {
                 sw_job_result r;
                 std::memset(&r, 0, sizeof(r));
@@ -766,9 +787,15 @@ extern "C" {
 
 const char *sw_last_error(void) { return g_err.c_str(); }
 
-sw_handle sw_create_replica(int model, int dim, int L, int q, double beta, uint64_t seed, uint32_t replica)
+sw_handle sw_create_tiled(int model, int dim, int L, int q, double beta, uint64_t seed, uint32_t replica,
+                          int tile)
 {
     g_err.clear();
+    if (tile < -1 || (tile >= 0 && tile >= num_tile_variants(model, dim))) {
+        fail(SW_E_INVALID, "unknown tile shape");
+        return nullptr;
+    }
+    if (tile < 0) tile = tuned_tile(model, dim, L);
     std::unique_ptr<sw_ctx> h(new sw_ctx());
     h->stream = make_stream();
     if (!h->stream) {
@@ -778,7 +805,7 @@ sw_handle sw_create_replica(int model, int dim, int L, int q, double beta, uint6
     h->own_stream = true;
     h->lat = new Lattice();
     h->owned = true;
-    int rc = h->lat->create(model, dim, L, q, beta, seed, replica, 0, h->stream);
+    int rc = h->lat->create(model, dim, L, q, beta, seed, replica, tile, h->stream);
     if (rc) {
         delete h->lat;
         (void)hipStreamDestroy(h->stream);
@@ -786,6 +813,82 @@ sw_handle sw_create_replica(int model, int dim, int L, int q, double beta, uint6
         return nullptr;
     }
     return h.release();
+}
+
+sw_handle sw_create_replica(int model, int dim, int L, int q, double beta, uint64_t seed, uint32_t replica)
+{
+    return sw_create_tiled(model, dim, L, q, beta, seed, replica, -1);
+}
+
+int sw_tile_count(int model, int dim)
+{
+    if (model < 0 || model > 2 || (dim != 2 && dim != 3)) return fail(SW_E_INVALID, "bad model or dim");
+    return num_tile_variants(model, dim);
+}
+
+int sw_tile_shape(int model, int dim, int tile, int *tx, int *ty, int *tz)
+{
+    if (model < 0 || model > 2 || (dim != 2 && dim != 3)) return fail(SW_E_INVALID, "bad model or dim");
+    if (tile < 0 || tile >= num_tile_variants(model, dim)) return fail(SW_E_INVALID, "unknown tile shape");
+    const TileShape t = tile_shape(model, dim, tile);
+    if (tx) *tx = t.tx;
+    if (ty) *ty = t.ty;
+    if (tz) *tz = dim == 3 ? t.tz : 1;
+    return SW_OK;
+}
+
+int sw_get_tile(sw_handle h)
+{
+    if (!h || !h->lat) return fail(SW_E_INVALID, "NULL handle");
+    return h->lat->variant;
+}
+
+int sw_tune(int model, int dim, int L, int q, double beta, int sweeps, int *best, double *ms_per_sweep)
+{
+    g_err.clear();
+    if (sweeps < 1 || sweeps > 100000) return fail(SW_E_INVALID, "sweeps must be in [1, 100000]");
+    int rc = validate(model, dim, L, model == ISING ? 2 : q, beta);
+    if (rc) return rc;
+    hipStream_t st = make_stream();
+    if (!st) return fail(SW_E_DEVICE, "hipStreamCreate failed (no HIP device?)");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        (void)hipStreamDestroy(st);
+        return fail(SW_E_DEVICE, "hipEventCreate failed");
+    }
+    const int nv = num_tile_variants(model, dim);
+    int arg = 0;
+    double tbest = 0.0;
+    for (int v = 0; v < nv && rc == SW_OK; ++v) {
+        Lattice lat;
+        rc = lat.create(model, dim, L, q, beta, 0x7e57ull + (uint64_t)v, 0, v, st);
+        if (rc == SW_OK) rc = lat.sweep_solo(2);
+        if (rc != SW_OK) break;
+        float ms = 0.0f;
+        if (hipEventRecord(e0, st) != hipSuccess) rc = fail(SW_E_DEVICE, "hipEventRecord failed");
+        if (rc == SW_OK) rc = lat.sweep_solo(sweeps);
+        if (rc == SW_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                            hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+            rc = fail(SW_E_DEVICE, "event timing failed");
+        if (rc != SW_OK) break;
+        const double per = (double)ms / sweeps;
+        if (ms_per_sweep) ms_per_sweep[v] = per;
+        if (v == 0 || per < tbest) {
+            tbest = per;
+            arg = v;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipStreamDestroy(st);
+    if (rc) return rc;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tuned[std::make_tuple(model, dim, L)] = arg;
+    }
+    if (best) *best = arg;
+    return SW_OK;
 }
 
 sw_handle sw_create(int model, int dim, int L, int q, double beta, uint64_t seed)
@@ -980,7 +1083,7 @@ sw_batch sw_batch_create(const sw_job_desc *jobs, int n)
     for (int j = 0; j < n; ++j) {
         std::unique_ptr<Lattice> l(new Lattice());
         int rc = l->create(jobs[j].model, jobs[j].dim, jobs[j].L, jobs[j].q, jobs[j].beta, jobs[j].seed,
-                           jobs[j].replica, 0, b->stream);
+                           jobs[j].replica, tuned_tile(jobs[j].model, jobs[j].dim, jobs[j].L), b->stream);
         if (rc) return nullptr;
         std::unique_ptr<sw_ctx> v(new sw_ctx());
         v->lat = l.get();

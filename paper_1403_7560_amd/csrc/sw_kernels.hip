@@ -3,21 +3,23 @@
 // One sweep (Sec. 2 of the paper: (1) active bonds, (2) cluster labelling,
 // (3) random state per cluster) is three launches per (model, dim) group:
 //
-//   k_bond   one workgroup per lattice tile.  Stages the tile and its +1 halo
-//            in LDS, draws the bond words (Philox4x32-10, one block per
-//            4 aligned sites and direction), forms the bonds, measures the
-//            incoming configuration, then labels the tile's clusters with a
-//            union-find in LDS (label equivalence resolved by atomicMin on
-//            roots, fixed point = minimum index).  Local roots receive their
-//            cluster decision; labels and the tile's two faces per direction
-//            go to HBM.
+//   k_bond   one workgroup per lattice tile, lane = tile column, each
+//            wavefront a block of rows in registers.  Draws the bond words
+//            (Philox4x32-10, one block per four rows of a column), forms the
+//            bonds, measures the incoming configuration, then labels the
+//            tile's clusters: a row-by-row scan of x-bond runs inheriting
+//            labels from the row above (label equivalence, fixed point =
+//            minimum index), with a union-find in LDS over run starts for the
+//            remaining equivalences.  Local roots receive their cluster
+//            decision; labels and the tile's two faces per direction go to HBM.
 //   k_merge  global label equivalence across tiles: for every active bond
 //            that crosses a tile face, link the larger root under the smaller
 //            with device-scope atomicMin (Hawick's atomicMin on R[label],
 //            retried until linked, so one pass reaches the fixed point).
-//            An extra grid slice reduces the per-tile measurement partials.
-//   k_flip   every site follows its label chain to the root and takes the
-//            root's decision (Ising +-1, Potts state, XY mirror).
+//   k_flip   every site takes its root's decision (Ising +-1, Potts state,
+//            XY mirror), following label -> tile root -> final root with the
+//            loads of all its rows in flight together.  The first workgroups
+//            also reduce the sweep's measurement.
 //
 // Kernels read a per-lattice descriptor and a tile map, so one launch covers
 // any number of lattices of one (model, dim) group (the batched form).
@@ -40,9 +42,9 @@ __device__ __forceinline__ uint4 philox(uint4 c, uint32_t k0, uint32_t k1)
 {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
-        const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
-        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+        const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c.x;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c.z;
+        c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ c.w ^ k1, (uint32_t)p0);
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }
@@ -57,30 +59,6 @@ __device__ __forceinline__ uint32_t lane_of(const uint4 &v, uint32_t lane)
     const uint32_t lo = v.x ^ ((v.x ^ v.y) & m1);
     const uint32_t hi = v.z ^ ((v.z ^ v.w) & m1);
     return lo ^ ((lo ^ hi) & m2);
-}
-
-__device__ __forceinline__ uint32_t comp(const uint4 &v, int c)
-{
-    return c == 0 ? v.x : (c == 1 ? v.y : (c == 2 ? v.z : v.w));
-}
-
-// The four words of sites gi0 .. gi0+3 from the Philox blocks gi0/4 (a) and
-// gi0/4 + 1 (b).  Aligned quads take the components in place.
-__device__ __forceinline__ void quad_words(uint32_t gi0, const uint4 &a, const uint4 &b, uint32_t w[4])
-{
-    const uint32_t off = gi0 & 3u;
-    if (off == 0) {
-        w[0] = a.x;
-        w[1] = a.y;
-        w[2] = a.z;
-        w[3] = a.w;
-    } else {
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            const uint32_t p = off + (uint32_t)m;
-            w[m] = (p < 4u) ? lane_of(a, p) : lane_of(b, p - 4u);
-        }
-    }
 }
 
 // Direction of the XY embedding at sweep n: a uniform angle from 53 bits of
@@ -232,8 +210,6 @@ __global__ void __launch_bounds__(256) k_init(const InstDesc *__restrict__ descs
 // Helpers of the bond kernel.
 // ---------------------------------------------------------------------------
 #define GLOBAL __attribute__((address_space(1)))
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 // Tile handled by this workgroup.  Workgroups are dealt to the 8 XCDs in
 // turn, so slot b's neighbour b+1 runs on another XCD; this ordering keeps
@@ -245,10 +221,38 @@ __device__ __forceinline__ int tile_slot()
     return (b & 7) * (nb >> 3) + (b >> 3);
 }
 
-// Bytes of t that are zero -> bit 7 of that byte set (exact per byte).
+// Bytes of t that are zero -> bit 7 of that byte set (exact per byte: the
+// masked sums cannot carry into the next byte).
 __device__ __forceinline__ uint32_t zero_bytes(uint32_t t)
 {
     return ~(((t & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | t) & 0x80808080u;
+}
+
+// Value held by lane + 1 of the wavefront (DPP wavefront shift; lane 63 gets 0).
+__device__ __forceinline__ uint32_t from_right(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x130, 0xf, 0xf, false);
+}
+
+// Value held by lane - 1 of the wavefront (lane 0 gets 0).
+__device__ __forceinline__ uint32_t from_left(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x138, 0xf, 0xf, false);
+}
+
+__device__ __forceinline__ double from_right_d(double v)
+{
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const uint32_t lo = from_right((uint32_t)u), hi = from_right((uint32_t)(u >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+__device__ __forceinline__ double readlane_d(double v, int l)
+{
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
 // The 16-bit secondary of bond (g, mu): high half of word d*g+mu of the tie
@@ -261,93 +265,97 @@ __device__ __noinline__ uint32_t bond_secondary(uint32_t key0, uint32_t key1, ui
     return lane_of(b, w & 3u) >> 16;
 }
 
-// Primaries (16 bits) of the bonds of sites gi0 .. gi0+3: x and y come from
-// word g of BOND (high and low half), z from word g/2 of BOND_Z (high half for
-// even g, low half for odd g).
-template <int DIM>
-__device__ __forceinline__ void quad_primaries(const InstDesc &d, uint32_t n, uint32_t gi0, int nv,
-                                               uint32_t px[4], uint32_t py[4], uint32_t pz[4])
+// XY bond test, exact form: u = (P 2^16 + S) 2^-32 < -expm1(-(2 beta s_i) s_j)
+// with s = cos(theta - phi) in FP64, decided from the 16-bit primary alone
+// unless u's interval straddles p.  The angles are re-read from HBM: this
+// runs only when the fast test below cannot decide.
+__device__ __noinline__ uint32_t xy_bond_exact(const float *th, uint32_t gi, uint32_t gj, double phi,
+                                               double two_beta, uint32_t p, uint32_t key0, uint32_t key1,
+                                               uint32_t rep, uint32_t n, int dim, int mu)
 {
-    const uint32_t b0 = gi0 >> 2;
-    const uint4 a = philox(make_uint4(b0, n, (uint32_t)TAG_BOND, d.rep), d.key0, d.key1);
-    uint32_t w[4];
-    if ((gi0 & 3u) == 0) {
-        w[0] = a.x;
-        w[1] = a.y;
-        w[2] = a.z;
-        w[3] = a.w;
-    } else {
-        uint4 b = a;
-        if ((gi0 & 3u) + (uint32_t)nv > 4u)
-            b = philox(make_uint4(b0 + 1u, n, (uint32_t)TAG_BOND, d.rep), d.key0, d.key1);
-        quad_words(gi0, a, b, w);
-    }
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-        px[m] = w[m] >> 16;
-        py[m] = w[m] & 0xffffu;
-    }
-    if (DIM == 3) {
-        // z words g/2 for g = gi0 .. gi0+3 lie in blocks gi0/8 and possibly gi0/8 + 1
-        const uint32_t zb0 = gi0 >> 3;
-        const uint4 za = philox(make_uint4(zb0, n, (uint32_t)TAG_BOND_Z, d.rep), d.key0, d.key1);
-        uint4 zb = za;
-        if (((gi0 + (uint32_t)nv - 1u) >> 3) != zb0)
-            zb = philox(make_uint4(zb0 + 1u, n, (uint32_t)TAG_BOND_Z, d.rep), d.key0, d.key1);
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            const uint32_t g = gi0 + (uint32_t)m;
-            const uint32_t idx = (g >> 1) - (zb0 << 2);  // 0 .. 5
-            const uint32_t word = (idx < 4u) ? lane_of(za, idx) : lane_of(zb, idx - 4u);
-            pz[m] = (g & 1u) ? (word & 0xffffu) : (word >> 16);
-        }
-    } else {
-#pragma unroll
-        for (int m = 0; m < 4; ++m) pz[m] = 0;
-    }
+    const double si = cos((double)th[gi] - phi), sj = cos((double)th[gj] - phi);
+    const double x = (two_beta * si) * sj;
+    const double pr = -expm1(-x);
+    const double lo = (double)p * 0x1p-16, hi = (double)(p + 1u) * 0x1p-16;
+    if (hi <= pr) return 1u;
+    if (lo >= pr) return 0u;
+    const uint32_t sec = bond_secondary(key0, key1, rep, n, dim, gi, mu);
+    return (double)((p << 16) | sec) * 0x1p-32 < pr ? 1u : 0u;
+}
+
+// XY bond test, fast form: p = 1 - e^-x in FP32 from x = (2 beta s_i) s_j,
+// the projections taken as cos(theta) cos(phi) + sin(theta) sin(phi) in FP64.
+// |p_fast - p_exact| stays below 3e-7 (FP64 projections ~1e-15, the float
+// rounding of x and of x log2(e), the exp2 instruction and the subtraction a
+// few float ulps each), so a primary interval that clears p_fast by
+// XY_MARGIN = 2^-18 decides the bond exactly as the FP64 rule would.
+// Returns 1 / 0, or 2 when undecided.
+#define XY_MARGIN 0x1p-18f
+__device__ __forceinline__ uint32_t xy_bond_fast(double two_beta, double si, double sj, uint32_t p)
+{
+    const float x = (float)((two_beta * si) * sj);
+    const float pf = 1.0f - __builtin_amdgcn_exp2f(x * -1.44269504088896340736f);
+    const float lo = (float)p * 0x1p-16f, hi = (float)(p + 1u) * 0x1p-16f;
+    if (hi <= pf - XY_MARGIN) return 1u;
+    if (lo >= pf + XY_MARGIN) return 0u;
+    return 2u;
 }
 
 // ---------------------------------------------------------------------------
 // Bond generation + tile-local labelling + measurement.
 // mode 0: full sweep step; mode 1: measurement of the configuration only.
+//
+// Lane c of every wavefront owns column c of the tile; wavefront w owns the
+// tile rows [w R, (w+1) R) (row r = y + TY z), kept in registers.  The x
+// neighbour comes from lane c+1 by a DPP shift (the tile's last column from a
+// halo column), the y and z neighbours from the same lane's other rows or a
+// halo row.  The bond words are the column blocks of the random layout: one
+// Philox call per lane gives the words of four consecutive rows.
+//
+// Labelling scans the rows in order: the x bonds of a row form runs (ballot
+// and bit tricks); a run takes the label of its leftmost site bonded to the
+// row above (3D: or the plane behind), otherwise its own start.  Only run
+// starts are union-find nodes: s_par[start] links to the inherited label.  A
+// bonded neighbour whose label differs is an equivalence, queued and resolved
+// in s_par (larger root under smaller) together with the bonds that cross
+// wavefront blocks and the periodic bonds of a tile that spans the lattice.
+// After path compression the root of a site is s_par[its run start].
 // ---------------------------------------------------------------------------
+template <int MODEL> struct LaneValue { typedef uint32_t type; };
+template <> struct LaneValue<XY> { typedef double type; };
+
+// Workgroups per CU the bond kernel is register-limited to: Ising / Potts as
+// many as its LDS allows (160 KB per CU), up to the 8 waves per SIMD of the
+// hardware; XY keeps its FP64 projections in registers and runs 4.
+template <int MODEL, int T> struct BondOccupancy {
+    static constexpr int value = (MODEL == XY) ? 4 : ((T <= 2048) ? 8 : ((T <= 4096) ? 7 : 3));
+};
+
 template <int MODEL, int DIM, int TX, int TY, int TZ>
-__global__ void __launch_bounds__(256) k_bond(const InstDesc *__restrict__ descs,
+__global__ void __launch_bounds__(256, (BondOccupancy<MODEL, TX * TY * TZ>::value))
+k_bond(const InstDesc *__restrict__ descs,
                                               const int2 *__restrict__ tmap, uint32_t k, int mode)
 {
     typedef typename StateOf<MODEL>::type S;
     constexpr int T = TX * TY * TZ;
-    constexpr int SX = TX + 4, SY = TY + 1, SZ = (DIM == 3) ? TZ + 1 : 1;  // rows padded to 4 bytes
-    constexpr int NH = SX * SY * SZ;
-    constexpr int QX = TX / 4;
-    constexpr int NQ = T / 4;
-    constexpr int QPT = NQ / 256;
     constexpr int ROWS = TY * TZ;
-    constexpr int R = ROWS / 4;  // rows scanned by each wavefront
+    constexpr int R = ROWS / 4;  // rows per wavefront
+    constexpr int NG = R / 4;    // groups of four rows per wavefront
     constexpr bool IS_XY = (MODEL == XY);
-    constexpr int QCAP = 256;    // per-wave queue of deferred equivalences
-    static_assert(TX == 64, "a tile row is one wavefront (lane = column) in the labelling scan");
-    static_assert(T <= 32768, "provisional labels are 16-bit");
-    static_assert(ROWS % 4 == 0, "whole rows per wavefront");
-    static_assert(NQ % 256 == 0, "whole quads per thread");
-    static_assert(DIM == 3 || TZ == 1, "2D tiles have TZ = 1");
+    constexpr int QCAP = 128;    // per-wave queue of deferred equivalences
+    constexpr int NONE = 0x7fffffff;
+    static_assert(TX == 64, "a tile row is one wavefront (lane = column)");
+    static_assert(R % 4 == 0 && R <= 32, "whole row groups, one bond bit per row");
+    static_assert(TY % 4 == 0, "row groups of the column random layout stay in a plane");
+    static_assert(DIM == 2 ? TZ == 1 : R % TY == 0, "3D: whole planes per wavefront");
 
-    // LDS: the staged states (or XY projections) are dead once the bonds are
-    // known, so the labelling arrays reuse that space.
-    constexpr int STAGE_BYTES = IS_XY ? NH * 16 : ((NH + 15) / 16) * 16;
-    constexpr int LABEL_BYTES = T * 4 + T * 2;
-    constexpr int REGION = STAGE_BYTES > LABEL_BYTES ? STAGE_BYTES : LABEL_BYTES;
-    __shared__ __align__(16) uint8_t s_mem[REGION];
-    __shared__ __align__(16) uint8_t s_bond[T];
-    __shared__ uint32_t s_cw[ROWS * 8];  // cluster decision words, 8 per tile row
+    __shared__ int s_par[T];
+    __shared__ unsigned long long s_xm[ROWS];  // in-tile x-bond mask of every row
+    __shared__ uint32_t s_cw[ROWS * 8];        // cluster decision words, 8 per tile row
     __shared__ uint32_t s_q[4][QCAP];
     __shared__ int s_hist[MODEL == POTTS ? 256 : 1];
     __shared__ double s_red[4][3];
-    __shared__ double s_phi;
-    S *s_st = (S *)s_mem;
-    double2 *s_sig = (double2 *)s_mem;
-    int *s_par = (int *)s_mem;
-    int16_t *s_plab = (int16_t *)(s_mem + T * 4);
+    __shared__ double s_phi[3];  // XY: phi, cos phi, sin phi
 
     const int2 tm = tmap[tile_slot()];
     if (tm.x < 0) return;
@@ -362,133 +370,46 @@ __global__ void __launch_bounds__(256) k_bond(const InstDesc *__restrict__ descs
     const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
     const int ex = min(TX, L - x0), ey = min(TY, L - y0), ez = (DIM == 3) ? min(TZ, L - z0) : 1;
     const int tid = threadIdx.x;
-    const int lane = tid & 63, wv = tid >> 6;
+    const int c = tid & 63, wv = tid >> 6;
+    const int r0 = wv * R;
+    const bool vc = c < ex;
     const bool full = (mode == 0);
     const bool meas = (mode == 1) || d.measure;
-    const bool bits_dec = (MODEL != POTTS) || d.q == 2;  // one decision bit per cluster
-    GLOBAL uint8_t *g_bond = (GLOBAL uint8_t *)d.bond;
+    const bool bits_dec = (MODEL != POTTS) || d.q == 2;
+    const uint32_t key0 = d.key0, key1 = d.key1, rep = d.rep;
+    const GLOBAL S *g_st = (const GLOBAL S *)d.state;
     GLOBAL uint32_t *g_label = (GLOBAL uint32_t *)d.label;
+    const uint32_t uL = (uint32_t)L;
+    const uint32_t gx = (uint32_t)(x0 + c);
+    const uint32_t gxr = (x0 + ex == L) ? 0u : (uint32_t)(x0 + ex);  // column right of the tile
 
-    auto gsite = [&](int lx, int ly, int lz) -> uint32_t {
-        return (uint32_t)(x0 + lx) + (uint32_t)L * ((uint32_t)(y0 + ly) + (uint32_t)L * (uint32_t)(z0 + lz));
+    // tile row j of this wavefront -> local y, z (2D: the wave holds part of
+    // the plane; 3D: whole planes)
+    auto row_y = [&](int j) -> int { return DIM == 2 ? r0 + j : j % TY; };
+    auto row_z = [&](int j) -> int { return DIM == 2 ? 0 : r0 / TY + j / TY; };
+    auto row_ok = [&](int j) -> bool { return row_y(j) < ey && row_z(j) < ez; };
+    // global index of (x, y0 + ly, z0 + lz), ly <= ey and lz <= ez wrapping
+    auto gat = [&](uint32_t x, int ly, int lz) -> uint32_t {
+        uint32_t y = (uint32_t)(y0 + ly), z = (uint32_t)(z0 + lz);
+        if (y >= uL) y -= uL;
+        if (DIM == 3 && z >= uL) z -= uL;
+        return x + uL * (y + uL * z);
+    };
+    auto gidx = [&](int l) -> uint32_t {  // tile-local index -> global index
+        const int row = l >> 6;
+        return (uint32_t)(x0 + (l & 63)) + uL * ((uint32_t)(y0 + row % TY) + uL * (uint32_t)(z0 + row / TY));
     };
 
-    if (IS_XY && tid == 0) s_phi = xy_phi(d, n);
+    if (IS_XY && tid == 0) {
+        const double ph = xy_phi(d, n);
+        double sp, cp;
+        sincos(ph, &sp, &cp);
+        s_phi[0] = ph;
+        s_phi[1] = cp;
+        s_phi[2] = sp;
+    }
     if (MODEL == POTTS && meas)
-        for (int c = tid; c < d.q; c += 256) s_hist[c] = 0;
-    if (IS_XY) __syncthreads();
-    const double phi = IS_XY ? s_phi : 0.0;
-
-    // ---- stage states (+1 halo in every + direction) ------------------------
-    // Interior: one 4-site load per quad, all issued before any LDS store.
-    {
-        uint32_t raw[QPT];
-        float4 rawf[QPT];
-#pragma unroll
-        for (int j = 0; j < QPT; ++j) {
-            const int qid = tid + 256 * j;
-            const int qx = qid % QX, row = qid / QX;
-            const int ly = row % TY, lz = row / TY;
-            const int lx0 = qx * 4;
-            raw[j] = 0;
-            rawf[j] = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (ly >= ey || lz >= ez || lx0 >= ex) continue;
-            const int nv = min(4, ex - lx0);
-            const uint32_t gi0 = gsite(lx0, ly, lz);
-            if ((gi0 & 3u) == 0 && nv == 4) {
-                if (IS_XY) {
-                    const f32x4 v = *(const GLOBAL f32x4 *)((const GLOBAL float *)d.state + gi0);
-                    rawf[j] = make_float4(v.x, v.y, v.z, v.w);
-                }
-                else raw[j] = *(const GLOBAL uint32_t *)((const GLOBAL uint8_t *)d.state + gi0);
-            } else if (IS_XY) {
-                const GLOBAL float *st = (const GLOBAL float *)d.state + gi0;
-                rawf[j].x = st[0];
-                if (nv > 1) rawf[j].y = st[1];
-                if (nv > 2) rawf[j].z = st[2];
-                if (nv > 3) rawf[j].w = st[3];
-            } else {
-                const GLOBAL uint8_t *st = (const GLOBAL uint8_t *)d.state + gi0;
-                for (int m = 0; m < nv; ++m) raw[j] |= (uint32_t)st[m] << (8 * m);
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < QPT; ++j) {
-            const int qid = tid + 256 * j;
-            const int qx = qid % QX, row = qid / QX;
-            const int ly = row % TY, lz = row / TY;
-            const int lx0 = qx * 4;
-            if (ly >= ey || lz >= ez || lx0 >= ex) continue;
-            const int nv = min(4, ex - lx0);
-            const int h = lx0 + SX * (ly + SY * lz);
-            // a partial quad stores only its own sites: the cell after it may be
-            // the +x halo, written by another thread
-            if (IS_XY) {
-                const float a[4] = {rawf[j].x, rawf[j].y, rawf[j].z, rawf[j].w};
-#pragma unroll
-                for (int m = 0; m < 4; ++m) {
-                    if (m >= nv) continue;
-                    double sv, cv;
-                    sincos((double)a[m] - phi, &sv, &cv);
-                    s_sig[h + m] = make_double2(cv, sv);
-                }
-            } else if (nv == 4) {
-                *(uint32_t *)&s_st[h] = raw[j];
-            } else {
-                for (int m = 0; m < nv; ++m) s_st[h + m] = (S)(raw[j] >> (8 * m));
-            }
-        }
-    }
-    // Halo: the +x column, the +y row and (3D) the +z layer of the tile.
-    {
-        constexpr int HX = TY * TZ, HY = TX * TZ, HZ = (DIM == 3) ? TX * TY : 0;
-        constexpr int NHALO = HX + HY + HZ;
-        constexpr int HPT = (NHALO + 255) / 256;
-        S hv[HPT];
-        int hh[HPT];
-#pragma unroll
-        for (int u = 0; u < HPT; ++u) {
-            const int c = tid + 256 * u;
-            hh[u] = -1;
-            int hx = 0, hy = 0, hz = 0;
-            if (c < HX) {
-                hx = ex;
-                hy = c % TY;
-                hz = c / TY;
-                if (hy >= ey || hz >= ez) continue;
-            } else if (c < HX + HY) {
-                hx = (c - HX) % TX;
-                hy = ey;
-                hz = (c - HX) / TX;
-                if (hx >= ex || hz >= ez) continue;
-            } else if (c < NHALO) {
-                hx = (c - HX - HY) % TX;
-                hy = (c - HX - HY) / TX;
-                hz = ez;
-                if (hx >= ex || hy >= ey) continue;
-            } else {
-                continue;
-            }
-            int gx = x0 + hx, gy = y0 + hy, gz = z0 + hz;
-            if (gx >= L) gx -= L;
-            if (gy >= L) gy -= L;
-            if (DIM == 3 && gz >= L) gz -= L;
-            const uint32_t gi = (uint32_t)gx + (uint32_t)L * ((uint32_t)gy + (uint32_t)L * (uint32_t)gz);
-            hv[u] = ((const GLOBAL S *)d.state)[gi];
-            hh[u] = hx + SX * (hy + SY * hz);
-        }
-#pragma unroll
-        for (int u = 0; u < HPT; ++u) {
-            if (hh[u] < 0) continue;
-            if (IS_XY) {
-                double sv, cv;
-                sincos((double)hv[u] - phi, &sv, &cv);
-                s_sig[hh[u]] = make_double2(cv, sv);
-            } else {
-                s_st[hh[u]] = hv[u];
-            }
-        }
-    }
+        for (int q = tid; q < d.q; q += 256) s_hist[q] = 0;
     // Cluster decision words of every tile row (one bit per possible root):
     // row r needs words g/32 for its sites g, which lie in Philox blocks
     // g_r/128 and g_r/128 + 1 of the cluster stream.
@@ -496,136 +417,268 @@ __global__ void __launch_bounds__(256) k_bond(const InstDesc *__restrict__ descs
         const int r = tid >> 1, half = tid & 1;
         const int ly = r % TY, lz = r / TY;
         if (ly < ey && lz < ez) {
-            const uint32_t gr = gsite(0, ly, lz);
-            const uint4 w = philox(make_uint4((gr >> 7) + (uint32_t)half, n, (uint32_t)TAG_CLUSTER, d.rep),
-                                   d.key0, d.key1);
+            const uint32_t gr = gat((uint32_t)x0, ly, lz);
+            const uint4 w = philox(make_uint4((gr >> 7) + (uint32_t)half, n, (uint32_t)TAG_CLUSTER, rep), key0, key1);
             *(uint4 *)&s_cw[8 * r + 4 * half] = w;
         }
     }
-    __syncthreads();
+    if (IS_XY || (MODEL == POTTS && meas)) __syncthreads();
+    const double phi = IS_XY ? s_phi[0] : 0.0, cphi = IS_XY ? s_phi[1] : 0.0, sphi = IS_XY ? s_phi[2] : 0.0;
 
-    // ---- (1) bonds and measurement -------------------------------------------
+    // ---- states of the wave's rows, their +y/+z rows and the +x halo column --
+    // Ising / Potts keep the states; XY keeps (cos theta, sin theta) in FP64.
+    typedef typename LaneValue<MODEL>::type V;
+    V own[R], ownS[R];
+    auto value_at = [&](uint32_t g, V &vs) -> V {
+        if constexpr (IS_XY) {
+            double sv, cv;
+            sincos((double)((const GLOBAL float *)d.state)[g], &sv, &cv);
+            vs = sv;
+            return cv;
+        } else {
+            vs = 0;
+            return (V)(uint8_t)g_st[g];
+        }
+    };
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        own[j] = 0;
+        ownS[j] = 0;
+        if (vc && row_ok(j)) own[j] = value_at(gat(gx, row_y(j), row_z(j)), ownS[j]);
+    }
+    // halo column: XY: lane j < R holds the site right of the tile in row j;
+    // Ising / Potts: lane g < NG holds that column's four rows of group g
+    V hx = 0, hxS = 0;
+    uint32_t hxg = 0;
+    if (IS_XY && c < R) {
+        const int ly = DIM == 2 ? r0 + c : c % TY, lz = DIM == 2 ? 0 : r0 / TY + c / TY;
+        if (ly < ey && lz < ez) hx = value_at(gat(gxr, ly, lz), hxS);
+    }
+    if (!IS_XY && c < NG) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int j = 4 * c + m;
+            const int ly = DIM == 2 ? r0 + j : j % TY, lz = DIM == 2 ? 0 : r0 / TY + j / TY;
+            if (ly < ey && lz < ez) hxg |= (uint32_t)(uint8_t)g_st[gat(gxr, ly, lz)] << (8 * m);
+        }
+    }
+
+    // ---- (1) bonds and measurement --------------------------------------------
+    // Bond bits of row j = 4 g + m sit at bit 8 m + 7 of bxg[g] / byg[g] / bzg[g]
+    // (+x, +y, +z): the byte layout of the four-rows-at-once tests below.
+    uint32_t bxg[NG], byg[NG], bzg[NG];
     int cnt_al = 0, cnt_m = 0;
     double e_acc = 0.0, sx_acc = 0.0, sy_acc = 0.0;
-    uint32_t qb[QPT];
+    const uint32_t thr_hi = d.thr_hi;
+    const uint32_t q4 = (uL + 3u) >> 2;  // column blocks per plane row
+    uint4 zw = make_uint4(0u, 0u, 0u, 0u);
+    // Ising / Potts: the states of a group's four rows packed one per byte
+    uint32_t P[NG];
+    if constexpr (!IS_XY) {
 #pragma unroll
-    for (int j = 0; j < QPT; ++j) {
-        qb[j] = 0;
-        const int qid = tid + 256 * j;
-        const int qx = qid % QX, row = qid / QX;
-        const int ly = row % TY, lz = row / TY;
-        const int lx0 = qx * 4;
-        if (ly >= ey || lz >= ez || lx0 >= ex) continue;
-        const int nv = min(4, ex - lx0);
-        const uint32_t vmask = (nv == 4) ? 0xffffffffu : ((1u << (8 * nv)) - 1u);
-        const uint32_t gi0 = gsite(lx0, ly, lz);
-        const int h = lx0 + SX * (ly + SY * lz);
-        uint32_t px[4], py[4], pz[4];
-        if (full) quad_primaries<DIM>(d, n, gi0, nv, px, py, pz);
-        uint32_t bq = 0;
+        for (int gi = 0; gi < NG; ++gi)
+            P[gi] = own[4 * gi] | (own[4 * gi + 1] << 8) | (own[4 * gi + 2] << 16) | (own[4 * gi + 3] << 24);
+    }
+#pragma unroll
+    for (int gi = 0; gi < NG; ++gi) {
+        const int jf = 4 * gi;
+        bxg[gi] = byg[gi] = bzg[gi] = 0;
+        if (!row_ok(jf)) continue;  // uniform: the group's first row is outside the lattice
+        const uint32_t gyf = (uint32_t)(y0 + row_y(jf)), gzf = (uint32_t)(z0 + row_z(jf));
+        uint4 w = make_uint4(0u, 0u, 0u, 0u);
+        if (full) {
+            w = philox(make_uint4(gx + uL * ((gyf >> 2) + q4 * gzf), n, (uint32_t)TAG_BOND, rep), key0, key1);
+            if (DIM == 3 && ((TY % 8) != 0 || (row_y(jf) % 8) == 0))
+                zw = philox(make_uint4(gx + uL * ((gyf >> 3) + ((uL + 7u) >> 3) * gzf), n, (uint32_t)TAG_BOND_Z, rep),
+                            key0, key1);
+        }
+        const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+        // z primaries of the group: lanes 0,1 of the BOND_Z block for y mod 8 < 4, else lanes 2,3
+        const bool zhi = (gyf & 4u) != 0;
+        const uint32_t zwa = zhi ? zw.z : zw.x, zwb = zhi ? zw.w : zw.y;
+        const uint32_t zs[4] = {zwa >> 16, zwa & 0xffffu, zwb >> 16, zwb & 0xffffu};
         if constexpr (!IS_XY) {
-            const uint32_t s = *(const uint32_t *)&s_st[h];
-            const uint32_t sn = (uint8_t)s_st[h + 4];
-            const uint32_t sxn = (s >> 8) | (sn << 24);
-            const uint32_t syn = *(const uint32_t *)&s_st[h + SX];
-            const uint32_t eqx = zero_bytes(s ^ sxn) & vmask;
-            const uint32_t eqy = zero_bytes(s ^ syn) & vmask;
-            uint32_t eqz = 0;
-            if (DIM == 3) eqz = zero_bytes(s ^ *(const uint32_t *)&s_st[h + SX * SY]) & vmask;
-            if (meas) {
-                cnt_al += __popc(eqx) + __popc(eqy) + __popc(eqz);
-                if (MODEL == ISING) cnt_m += nv - 2 * __popc(s & 0x80808080u & vmask);
-                else {
+            // rows of the group inside the lattice, bit 7 of their byte
+            uint32_t vb = 0;
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+                if (row_ok(jf + m)) vb |= 0x80u << (8 * m);
+            if (!vc) vb = 0;
+            // +y neighbours: the group shifted by one row, the fifth row from the
+            // next group, a load across the wave block, or the wrapped row
+            uint32_t PU = 0;
+            const int l3 = row_y(jf + 3), z3 = row_z(jf + 3);
+            if (row_ok(jf + 3)) {
+                uint32_t nb;
+                const bool nb_own = DIM == 2 ? (jf + 4 < R && l3 + 1 < ey) : (l3 + 1 < TY && l3 + 1 < ey);
+                if (nb_own) nb = P[gi + 1 < NG ? gi + 1 : gi] & 0xffu;
+                else nb = vc ? (uint32_t)(uint8_t)g_st[gat(gx, l3 + 1, z3)] : 0u;
+                PU = __builtin_amdgcn_alignbyte(nb, P[gi], 1);
+            } else {
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    const int j = jf + m;
+                    if (!row_ok(j)) continue;
+                    uint32_t ub;
+                    if (row_y(j) + 1 < ey && m < 3) ub = (P[gi] >> (8 * (m + 1))) & 0xffu;
+                    else ub = vc ? (uint32_t)(uint8_t)g_st[gat(gx, row_y(j) + 1, row_z(j))] : 0u;
+                    PU |= ub << (8 * m);
+                }
+            }
+            // +z neighbours: the group one plane ahead in this wave, else loads
+            uint32_t PZ = 0;
+            if (DIM == 3) {
+                const int lz = row_z(jf);
+                if (jf + TY < R && lz + 1 < ez) {
+                    PZ = P[gi + TY / 4 < NG ? gi + TY / 4 : gi];
+                } else if (vc) {
 #pragma unroll
                     for (int m = 0; m < 4; ++m)
-                        if (m < nv) atomicAdd(&s_hist[(s >> (8 * m)) & 0xffu], 1);
+                        if (row_ok(jf + m))
+                            PZ |= (uint32_t)(uint8_t)g_st[gat(gx, row_y(jf + m), lz + 1)] << (8 * m);
+                }
+            }
+            // +x neighbours: lane c + 1, the last column from the halo
+            uint32_t PR = from_right(P[gi]);
+            if (c == ex - 1) PR = (uint32_t)__builtin_amdgcn_readlane((int)hxg, gi);
+            const uint32_t EQX = zero_bytes(P[gi] ^ PR) & vb;
+            const uint32_t EQY = zero_bytes(P[gi] ^ PU) & vb;
+            const uint32_t EQZ = (DIM == 3) ? (zero_bytes(P[gi] ^ PZ) & vb) : 0u;
+            if (meas) {
+                cnt_al += __popc(EQX) + __popc(EQY) + __popc(EQZ);
+                if (MODEL == ISING) {
+                    cnt_m += __popc(vb) - 2 * __popc(P[gi] & vb);
+                } else {
+#pragma unroll
+                    for (int m = 0; m < 4; ++m)
+                        if (vb & (0x80u << (8 * m))) atomicAdd(&s_hist[(P[gi] >> (8 * m)) & 0xffu], 1);
                 }
             }
             if (full) {
-                const uint32_t th = d.thr_hi;
-                uint32_t tie = 0;
+                // primary < threshold high half, per row, moved to bit 7 of the row's byte
+                uint32_t tx[4], ty_[4], tz_[4];
 #pragma unroll
                 for (int m = 0; m < 4; ++m) {
-                    const uint32_t ax = (eqx >> (8 * m + 7)) & 1u, ay = (eqy >> (8 * m + 7)) & 1u;
-                    const uint32_t az = (eqz >> (8 * m + 7)) & 1u;
-                    uint32_t bm = (ax & (px[m] < th)) | ((ay & (py[m] < th)) << 1);
-                    if (DIM == 3) bm |= (az & (pz[m] < th)) << 2;
-                    bq |= bm << (8 * m);
-                    tie |= (ax & (px[m] == th)) | (ay & (py[m] == th)) | (az & (pz[m] == th));
+                    tx[m] = (ws[m] >> 16) - thr_hi;
+                    ty_[m] = (ws[m] & 0xffffu) - thr_hi;
+                    tz_[m] = zs[m] - thr_hi;
                 }
-                if (tie) {  // rare: the primary equals the threshold's high half
+                const uint32_t LTX = __builtin_amdgcn_perm(tx[1], tx[0], 0x0c0c0703u) |
+                                     __builtin_amdgcn_perm(tx[3], tx[2], 0x07030c0cu);
+                const uint32_t LTY = __builtin_amdgcn_perm(ty_[1], ty_[0], 0x0c0c0703u) |
+                                     __builtin_amdgcn_perm(ty_[3], ty_[2], 0x07030c0cu);
+                bxg[gi] = LTX & EQX;
+                byg[gi] = LTY & EQY;
+                if (DIM == 3) {
+                    const uint32_t LTZ = __builtin_amdgcn_perm(tz_[1], tz_[0], 0x0c0c0703u) |
+                                         __builtin_amdgcn_perm(tz_[3], tz_[2], 0x07030c0cu);
+                    bzg[gi] = LTZ & EQZ;
+                }
+                // a primary equal to the threshold's high half needs the secondary (rare)
+                uint32_t tmin = min(min(min(tx[0], tx[1]), min(tx[2], tx[3])), min(min(ty_[0], ty_[1]), min(ty_[2], ty_[3])));
+                if (DIM == 3) tmin = min(tmin, min(min(tz_[0], tz_[1]), min(tz_[2], tz_[3])));
+                if (tmin == 0u) {
 #pragma unroll
                     for (int m = 0; m < 4; ++m) {
-                        const uint32_t g = gi0 + (uint32_t)m;
-                        const uint32_t p[3] = {px[m], py[m], pz[m]};
-                        const uint32_t eq[3] = {eqx, eqy, eqz};
-#pragma unroll
-                        for (int mu = 0; mu < DIM; ++mu)
-                            if (((eq[mu] >> (8 * m + 7)) & 1u) && p[mu] == th &&
-                                bond_secondary(d.key0, d.key1, d.rep, n, DIM, g, mu) < d.thr_lo)
-                                bq |= 1u << (8 * m + mu);
+                        const uint32_t bit = 0x80u << (8 * m);
+                        const uint32_t g = gat(gx, row_y(jf + m), row_z(jf + m));
+                        if ((EQX & bit) && tx[m] == 0u && bond_secondary(key0, key1, rep, n, DIM, g, 0) < d.thr_lo)
+                            bxg[gi] |= bit;
+                        if ((EQY & bit) && ty_[m] == 0u && bond_secondary(key0, key1, rep, n, DIM, g, 1) < d.thr_lo)
+                            byg[gi] |= bit;
+                        if (DIM == 3 && (EQZ & bit) && tz_[m] == 0u &&
+                            bond_secondary(key0, key1, rep, n, DIM, g, 2) < d.thr_lo)
+                            bzg[gi] |= bit;
                     }
                 }
             }
         } else {
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
-                if (m >= nv) continue;
-                const int hm = h + m;
-                const double2 a = s_sig[hm];
-                if (meas) {
-                    sx_acc += a.x;
-                    sy_acc += a.y;
+                const int j = jf + m;
+                if (!row_ok(j)) continue;
+                const int ly = row_y(j), lz = row_z(j);
+                // +y neighbour: the next row of this wave, else a load (halo or next wave)
+                V up, upS;
+                if (DIM == 2 ? (j + 1 < R && ly + 1 < ey) : (ly + 1 < min(TY, ey))) {
+                    up = own[j + 1 < R ? j + 1 : j];
+                    upS = ownS[j + 1 < R ? j + 1 : j];
+                } else {
+                    up = 0;
+                    upS = 0;
+                    if (vc) up = value_at(gat(gx, ly + 1, lz), upS);
                 }
-                const uint32_t p[3] = {px[m], py[m], pz[m]};
-#pragma unroll
-                for (int mu = 0; mu < DIM; ++mu) {
-                    const int hn = hm + (mu == 0 ? 1 : (mu == 1 ? SX : SX * SY));
-                    const double2 c = s_sig[hn];
-                    if (meas) e_acc -= a.x * c.x + a.y * c.y;
-                    if (full) {
-                        // u = (P 2^16 + S) 2^-32 against p = -expm1(-(2 beta s_i) s_j)
-                        const double x = (d.two_beta * a.x) * c.x;
-                        const double pr = -expm1(-x);
-                        const double lo = (double)p[mu] * 0x1p-16, hi = (double)(p[mu] + 1u) * 0x1p-16;
-                        bool on;
-                        if (hi <= pr) on = true;
-                        else if (lo >= pr) on = false;
-                        else {
-                            const uint32_t sec = bond_secondary(d.key0, d.key1, d.rep, n, DIM, gi0 + (uint32_t)m, mu);
-                            on = (double)((p[mu] << 16) | sec) * 0x1p-32 < pr;
-                        }
-                        if (on) bq |= 1u << (8 * m + mu);
+                V zn = 0, znS = 0;
+                if (DIM == 3) {
+                    if (j + TY < R && lz + 1 < ez) {
+                        zn = own[j + TY < R ? j + TY : j];
+                        znS = ownS[j + TY < R ? j + TY : j];
+                    } else if (vc) {
+                        zn = value_at(gat(gx, ly, lz + 1), znS);
                     }
                 }
-            }
-        }
-        qb[j] = bq;
-        if (full) {
-            *(uint32_t *)&s_bond[lx0 + TX * (ly + TY * lz)] = bq;
-            if (d.store_bonds) {
-                if ((gi0 & 3u) == 0 && nv == 4) {
-                    *(GLOBAL uint32_t *)(g_bond + gi0) = bq;
-                } else {
-                    for (int m = 0; m < nv; ++m) g_bond[gi0 + m] = (uint8_t)(bq >> (8 * m));
+                V rt = from_right_d(own[j]), rtS = from_right_d(ownS[j]);
+                if (c == ex - 1) {
+                    rt = readlane_d(hx, j);
+                    rtS = readlane_d(hxS, j);
+                }
+                const uint32_t g = gat(gx, ly, lz);
+                if (meas && vc) {
+                    sx_acc += own[j];
+                    sy_acc += ownS[j];
+                    e_acc -= own[j] * rt + ownS[j] * rtS;
+                    e_acc -= own[j] * up + ownS[j] * upS;
+                    if (DIM == 3) e_acc -= own[j] * zn + ownS[j] * znS;
+                }
+                if (full && vc) {
+                    const uint32_t px = ws[m] >> 16, py = ws[m] & 0xffffu, pz = zs[m];
+                    const double si = own[j] * cphi + ownS[j] * sphi;
+                    uint32_t onx = xy_bond_fast(d.two_beta, si, rt * cphi + rtS * sphi, px);
+                    uint32_t ony = xy_bond_fast(d.two_beta, si, up * cphi + upS * sphi, py);
+                    uint32_t onz = 0;
+                    if (DIM == 3) onz = xy_bond_fast(d.two_beta, si, zn * cphi + znS * sphi, pz);
+                    if ((onx | ony | onz) & 2u) {  // rare: p within the margin of the primary interval
+                        const float *th = (const float *)d.state;
+                        if (onx == 2u)
+                            onx = xy_bond_exact(th, g, (c == ex - 1) ? gat(gxr, ly, lz) : g + 1u, phi, d.two_beta,
+                                                px, key0, key1, rep, n, DIM, 0);
+                        if (ony == 2u)
+                            ony = xy_bond_exact(th, g, gat(gx, ly + 1, lz), phi, d.two_beta, py, key0, key1, rep, n,
+                                                DIM, 1);
+                        if (DIM == 3 && onz == 2u)
+                            onz = xy_bond_exact(th, g, gat(gx, ly, lz + 1), phi, d.two_beta, pz, key0, key1, rep, n,
+                                                DIM, 2);
+                    }
+                    bxg[gi] |= onx << (8 * m + 7);
+                    byg[gi] |= ony << (8 * m + 7);
+                    bzg[gi] |= onz << (8 * m + 7);
                 }
             }
         }
+        if (full && d.store_bonds && vc) {
+            // bond byte of each row: bit mu = bond to the +mu neighbour
+            const uint32_t B = (bxg[gi] >> 7) | (byg[gi] >> 6) | (bzg[gi] >> 5);
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+                if (row_ok(jf + m))
+                    ((GLOBAL uint8_t *)d.bond)[gat(gx, row_y(jf + m), row_z(jf + m))] = (uint8_t)(B >> (8 * m));
+        }
     }
+    auto bit_of = [&](const uint32_t *arr, int j) -> uint32_t { return (arr[j >> 2] >> (8 * (j & 3) + 7)) & 1u; };
 
     // ---- measurement partials of this tile -----------------------------------
     if (meas) {
         GLOBAL int64_t *part = (GLOBAL int64_t *)d.part + (int64_t)t * d.nslots;
         if (IS_XY) {
-            const double a = wave_sum_d(e_acc), b = wave_sum_d(sx_acc), c = wave_sum_d(sy_acc);
-            if (lane == 0) {
+            const double a = wave_sum_d(e_acc), b = wave_sum_d(sx_acc), cc = wave_sum_d(sy_acc);
+            if (c == 0) {
                 s_red[wv][0] = a;
                 s_red[wv][1] = b;
-                s_red[wv][2] = c;
+                s_red[wv][2] = cc;
             }
         } else {
             const int a = wave_sum_i(cnt_al), b = wave_sum_i(cnt_m);
-            if (lane == 0) {
+            if (c == 0) {
                 s_red[wv][0] = (double)a;
                 s_red[wv][1] = (double)b;
             }
@@ -633,276 +686,250 @@ __global__ void __launch_bounds__(256) k_bond(const InstDesc *__restrict__ descs
         __syncthreads();
         if (tid == 0) {
             if (IS_XY) {
-                for (int c = 0; c < 3; ++c) {
-                    const double v = ((s_red[0][c] + s_red[1][c]) + s_red[2][c]) + s_red[3][c];
-                    part[c] = __double_as_longlong(v);
+                for (int q = 0; q < 3; ++q) {
+                    const double v = ((s_red[0][q] + s_red[1][q]) + s_red[2][q]) + s_red[3][q];
+                    part[q] = __double_as_longlong(v);
                 }
             } else {
                 part[0] = (int64_t)(s_red[0][0] + s_red[1][0] + s_red[2][0] + s_red[3][0]);
-                if (MODEL == ISING)
-                    part[1] = (int64_t)(s_red[0][1] + s_red[1][1] + s_red[2][1] + s_red[3][1]);
+                if (MODEL == ISING) part[1] = (int64_t)(s_red[0][1] + s_red[1][1] + s_red[2][1] + s_red[3][1]);
             }
         }
         if (MODEL == POTTS)
-            for (int c = tid; c < d.q; c += 256) part[1 + c] = s_hist[c];
+            for (int q = tid; q < d.q; q += 256) part[1 + q] = s_hist[q];
     }
     if (!full) return;
-    __syncthreads();  // s_bond complete; staged states no longer needed
-    for (int l = tid; l < T; l += 256) s_par[l] = l;
-    __syncthreads();
 
-    // ---- (2) local labelling: a row-by-row scan per wavefront ------------------
-    // Lane c of a wavefront owns column c of the tile; each of the four waves
-    // scans its own block of R rows (row r = y + TY z) in order.  In a row the
-    // x bonds form runs (ballot + bit tricks); a run takes the label of its
-    // leftmost site bonded to the row above (or, in 3D, the plane behind) and
-    // otherwise its own start index.  A bonded neighbour whose label differs
-    // from its run's label is an equivalence, queued and resolved afterwards
-    // in the union-find table s_par (larger root under smaller), together
-    // with the bonds across wave blocks and the periodic bonds inside a tile
-    // that spans the lattice.  The root of site l is then s_par[s_plab[l]].
-    constexpr int NONE = 0x7fffffff;
+    // ---- (2) local labelling ---------------------------------------------------
+    const unsigned long long upto = (c == 63) ? ~0ull : ((2ull << c) - 1ull);
+    const unsigned long long from = ~((1ull << c) - 1ull);
     int qn = 0;  // entries in this wave's queue (uniform)
     auto flush = [&]() {
-        for (int e = lane; e < qn; e += 64) {
+        for (int e = c; e < qn; e += 64) {
             const uint32_t pr = s_q[wv][e];
             lds_union(s_par, (int)(pr >> 16), (int)(pr & 0xffffu));
         }
         qn = 0;
     };
     auto push = [&](bool want, int a, int b) {
-        if (qn > QCAP - 64) flush();
         const unsigned long long m = __ballot(want);
+        if (!m) return;
+        if (qn > QCAP - 64) flush();
         if (want) {
-            const int pos = qn + __popcll(m & ((1ull << lane) - 1ull));
+            const int pos = qn + __popcll(m & ((1ull << c) - 1ull));
             s_q[wv][pos] = ((uint32_t)a << 16) | (uint32_t)b;
         }
         qn += __popcll(m);
     };
+    int labr[R];  // label of the run of (c, row j): a union-find node of this tile
     {
-        const int c = lane;
-        const int r0 = wv * R;
-        const unsigned long long upto = (c == 63) ? ~0ull : ((2ull << c) - 1ull);
-        const unsigned long long from = ~((1ull << c) - 1ull);
         int prevlab = NONE;
-        uint32_t prevb = 0;
-        for (int r = r0; r < r0 + R; ++r) {
-            const int y = r % TY, z = r / TY;
-            if (y >= ey || z >= ez) {  // ragged tile: rows past the lattice edge
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            labr[j] = NONE;
+            if (!row_ok(j)) {  // ragged tile: rows past the lattice edge
                 prevlab = NONE;
-                prevb = 0;
                 continue;
             }
-            const int l = c + TX * r;
-            const bool vc = c < ex;
-            const uint32_t b = vc ? s_bond[l] : 0u;
-            const unsigned long long xb = __ballot(vc && (b & 1u) && c + 1 < ex);
-            const unsigned long long brk = ~(xb << 1);  // bit c: a run starts at c
-            const int rs = 63 - __clzll((long long)(brk & upto));
+            const int rr = r0 + j;
+            const unsigned long long xb = __ballot(vc && bit_of(bxg, j) && c + 1 < ex);
+            if (c == 0) s_xm[rr] = xb;
+            const int rs = 63 - __clzll((long long)(~(xb << 1) & upto));
             const int re = __ffsll((long long)(~xb & from)) - 1;
             int ca = NONE, cb = NONE;
-            if (y > 0 && r - 1 >= r0 && (prevb & 2u)) ca = prevlab;
-            if (DIM == 3 && z > 0 && r - TY >= r0 && (s_bond[l - TX * TY] & 4u)) cb = s_plab[l - TX * TY];
-            const int cand = vc ? min(ca, cb) : NONE;
+            if (j > 0 && row_y(j) > 0 && bit_of(byg, j > 0 ? j - 1 : 0)) ca = prevlab;
+            if (DIM == 3 && j >= TY && bit_of(bzg, j >= TY ? j - TY : 0)) cb = labr[j >= TY ? j - TY : 0];
+            if (!vc) ca = cb = NONE;
+            const int cand = min(ca, cb);
             const unsigned long long conn = __ballot(cand != NONE);
             const unsigned long long mr = conn >> rs;
             const int f = mr ? rs + __ffsll((long long)mr) - 1 : 64;
             const int fl = __shfl(cand, f & 63, 64);
-            const int lab = (f <= re) ? fl : rs + TX * r;
-            if (vc) s_plab[l] = (int16_t)lab;
-            push(vc && ca != NONE && ca != lab, ca, lab);
-            if (DIM == 3) push(vc && cb != NONE && cb != lab, cb, lab);
+            const int node = rs + TX * rr;
+            const int lab = (f <= re) ? fl : node;
+            if (vc && c == rs) s_par[node] = lab;
+            // a bonded neighbour with another label: one entry per stretch of equal labels
+            const int cal = (int)from_left((uint32_t)ca);
+            push(ca != NONE && ca != lab && (c == rs || cal != ca), ca, lab);
+            if (DIM == 3) {
+                const int cbl = (int)from_left((uint32_t)cb);
+                push(cb != NONE && cb != lab && (c == rs || cbl != cb), cb, lab);
+            }
+            // periodic x bond of a tile that spans the lattice: to (0, row)
+            if (d.tiles[0] == 1) push(vc && c == ex - 1 && bit_of(bxg, j), TX * rr, lab);
             prevlab = lab;
-            prevb = b;
+            labr[j] = lab;
         }
     }
-    __syncthreads();  // all provisional labels written
-    // bonds between wave blocks and periodic bonds inside a tile spanning L
-    {
-        const int c = lane;
-        const int r0 = wv * R;
-        const bool vc = c < ex;
-        for (int r = r0; r < r0 + R; ++r) {
-            const int y = r % TY, z = r / TY;
-            if (y >= ey || z >= ez) continue;
-            const int l = c + TX * r;
-            const uint32_t b = vc ? s_bond[l] : 0u;
-            const int own = vc ? s_plab[l] : 0;
-            // the row above lies in the previous wave's block
-            const bool wy = vc && y > 0 && r - 1 < r0 && (s_bond[l - TX] & 2u);
-            push(wy, wy ? s_plab[l - TX] : 0, own);
-            // the plane behind lies in an earlier wave's block
-            if (DIM == 3) {
-                const bool wz = vc && z > 0 && r - TY < r0 && (s_bond[l - TX * TY] & 4u);
-                push(wz, wz ? s_plab[l - TX * TY] : 0, own);
-            }
-            const bool px_ = vc && (b & 1u) && c + 1 == ex && d.tiles[0] == 1;
-            push(px_, px_ ? s_plab[l - c] : 0, own);
-            const bool py_ = vc && (b & 2u) && y + 1 == ey && d.tiles[1] == 1;
-            push(py_, py_ ? s_plab[l - TX * y] : 0, own);
-            if (DIM == 3) {
-                const bool pz_ = vc && (b & 4u) && z + 1 == ez && d.tiles[2] == 1;
-                push(pz_, pz_ ? s_plab[l - TX * TY * z] : 0, own);
-            }
-        }
-        flush();
-    }
-    __syncthreads();
-    for (int l = tid; l < T; l += 256) s_par[l] = lds_find(s_par, l);
-    __syncthreads();
-    // root (tile-local index) of site l
-    auto root_of = [&](int l) -> int { return s_par[s_plab[l]]; };
-    auto gidx = [&](int r) -> uint32_t {
-        const int rx = r % TX, ry = (r / TX) % TY, rz = r / (TX * TY);
-        return gsite(rx, ry, rz);
+    __syncthreads();  // every row's x mask and run-start links written
+    // run-start node of site (c, tile row r)
+    auto node_of = [&](int r) -> int {
+        const unsigned long long xm = s_xm[r];
+        return (63 - __clzll((long long)(~(xm << 1) & upto))) + TX * r;
     };
-
-    // ---- local roots draw the cluster decision; labels to HBM -----------------
 #pragma unroll
-    for (int j = 0; j < QPT; ++j) {
-        const int qid = tid + 256 * j;
-        const int qx = qid % QX, row = qid / QX;
-        const int ly = row % TY, lz = row / TY;
-        const int lx0 = qx * 4;
-        if (ly >= ey || lz >= ez || lx0 >= ex) continue;
-        const int nv = min(4, ex - lx0);
-        const uint32_t gi0 = gsite(lx0, ly, lz);
-        const int l0 = lx0 + TX * (ly + TY * lz);
-        const uint2 pl = *(const uint2 *)&s_plab[l0];
-        const int p4[4] = {(int)(int16_t)(pl.x & 0xffffu), (int)(int16_t)(pl.x >> 16),
-                           (int)(int16_t)(pl.y & 0xffffu), (int)(int16_t)(pl.y >> 16)};
-        int rq[4];
+    for (int j = 0; j < R; ++j) {
+        if (!row_ok(j)) continue;
+        const int rr = r0 + j, ly = row_y(j), lz = row_z(j);
+        const bool oy = vc && bit_of(byg, j), oz = vc && bit_of(bzg, j);
+        // +y bond into the next wavefront's block (2D)
+        if (DIM == 2 && j == R - 1 && ly + 1 < ey) push(oy, node_of(rr + 1), node_of(rr));
+        // +z bond into the next wavefront's block (3D)
+        if (DIM == 3 && j + TY >= R && lz + 1 < ez) push(oz, node_of(rr + TY < ROWS ? rr + TY : rr), node_of(rr));
+        // periodic bonds of a tile that spans the lattice
+        if (ly == ey - 1 && d.tiles[1] == 1) push(oy, node_of(TY * lz), node_of(rr));
+        if (DIM == 3 && lz == ez - 1 && d.tiles[2] == 1) push(oz, node_of(ly), node_of(rr));
+    }
+    flush();
+    __syncthreads();
+    // root of every row's label: pointer jumping on all rows at once (the
+    // parents only ever point to smaller nodes, so this ends)
+    int root[R];
 #pragma unroll
-        for (int m = 0; m < 4; ++m) rq[m] = (m < nv) ? s_par[p4[m]] : -1;
-        bool anyroot = false;
+    for (int j = 0; j < R; ++j) root[j] = (vc && row_ok(j)) ? labr[j] : -1;
+    bool moving = true;
+    while (__any(moving)) {
+        moving = false;
 #pragma unroll
-        for (int m = 0; m < 4; ++m) anyroot |= (rq[m] == l0 + m);
-        uint32_t dec[4] = {0u, 0u, 0u, 0u};
-        if (anyroot) {
-            if (bits_dec) {
-                const uint32_t gr = gsite(0, ly, lz);
-                const uint32_t base = (gr >> 7) << 2;
-#pragma unroll
-                for (int m = 0; m < 4; ++m) {
-                    const uint32_t g = gi0 + (uint32_t)m;
-                    dec[m] = (s_cw[8 * row + (int)((g >> 5) - base)] >> (g & 31u)) & 1u;
-                }
-            } else {
-                const uint4 c1 = philox(make_uint4(gi0 >> 2, n, (uint32_t)TAG_CLUSTER, d.rep), d.key0, d.key1);
-                uint4 c2 = c1;
-                if ((gi0 & 3u) + (uint32_t)nv > 4u)
-                    c2 = philox(make_uint4((gi0 >> 2) + 1u, n, (uint32_t)TAG_CLUSTER, d.rep), d.key0, d.key1);
-                uint32_t cw[4];
-                quad_words(gi0, c1, c2, cw);
-#pragma unroll
-                for (int m = 0; m < 4; ++m) dec[m] = (uint32_t)(((uint64_t)cw[m] * (uint64_t)d.q) >> 32);
+        for (int j = 0; j < R; ++j) {
+            if (root[j] < 0) continue;
+            const int p = s_par[root[j]];
+            if (p != root[j]) {
+                root[j] = p;
+                moving = true;
             }
         }
-        uint32_t lab[4] = {0u, 0u, 0u, 0u};
+    }
+
+    // ---- local roots draw the cluster decision; labels and faces to HBM -------
+    const int F0 = d.face_len[0], F1 = d.face_len[1], F2 = (DIM == 3) ? d.face_len[2] : 0;
+    GLOBAL int32_t *fo0 = (GLOBAL int32_t *)d.face + d.face_off[0] + (int64_t)t * 2 * F0;
+    GLOBAL int32_t *fo1 = (GLOBAL int32_t *)d.face + d.face_off[1] + (int64_t)t * 2 * F1;
+    GLOBAL int32_t *fo2 = (GLOBAL int32_t *)d.face + d.face_off[DIM == 3 ? 2 : 0] + (int64_t)t * 2 * F2;
+    const bool fx = d.tiles[0] > 1, fy = d.tiles[1] > 1, fz = (DIM == 3) && d.tiles[2] > 1;
+#pragma unroll
+    for (int gi = 0; gi < NG; ++gi) {
+        const int jf = 4 * gi;
+        if (!row_ok(jf)) continue;
+        bool isr[4];
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
-            if (m >= nv) continue;
-            lab[m] = (rq[m] == l0 + m) ? (ROOT_FLAG | dec[m]) : gidx(rq[m]);
+            const int j = jf + m, rr = r0 + j;
+            isr[m] = row_ok(j) && vc && root[j] == c + TX * rr;
         }
-        if ((gi0 & 3u) == 0 && nv == 4) {
-            *(GLOBAL u32x4 *)(g_label + gi0) = (u32x4){lab[0], lab[1], lab[2], lab[3]};
-        } else {
+        uint32_t dec[4] = {0u, 0u, 0u, 0u};
+        if (bits_dec) {
 #pragma unroll
-            for (int m = 0; m < 4; ++m)
-                if (m < nv) g_label[gi0 + m] = lab[m];
+            for (int m = 0; m < 4; ++m) {
+                const int j = jf + m, rr = r0 + j;
+                if (!isr[m]) continue;
+                const uint32_t g = gat(gx, row_y(j), row_z(j));
+                const uint32_t base = (gat((uint32_t)x0, row_y(j), row_z(j)) >> 7) << 2;
+                dec[m] = (s_cw[8 * rr + (int)((g >> 5) - base)] >> (g & 31u)) & 1u;
+            }
+        } else if (__ballot(isr[0] || isr[1] || isr[2] || isr[3])) {
+            const uint32_t gyf = (uint32_t)(y0 + row_y(jf)), gzf = (uint32_t)(z0 + row_z(jf));
+            const uint4 w = philox(make_uint4(gx + uL * ((gyf >> 2) + q4 * gzf), n, (uint32_t)TAG_CLUSTER, rep), key0, key1);
+            const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+            for (int m = 0; m < 4; ++m) dec[m] = (uint32_t)(((uint64_t)ws[m] * (uint64_t)d.q) >> 32);
         }
-    }
-
-    // ---- faces for the global merge --------------------------------------------
 #pragma unroll
-    for (int mu = 0; mu < DIM; ++mu) {
-        if (d.tiles[mu] == 1) continue;
-        const int F = d.face_len[mu];
-        GLOBAL int32_t *fo = (GLOBAL int32_t *)d.face + d.face_off[mu] + (int64_t)t * 2 * F;
-        GLOBAL int32_t *fi = fo + F;
-        const int emu = (mu == 0) ? ex : (mu == 1 ? ey : ez);
-        for (int kk = tid; kk < F; kk += 256) {
-            int a, b;  // transverse coordinates
-            bool valid;
-            int lo, li;
-            if (mu == 0) {
-                a = kk % TY;
-                b = kk / TY;
-                valid = a < ey && b < ez;
-                lo = (emu - 1) + TX * (a + TY * b);
-                li = 0 + TX * (a + TY * b);
-            } else if (mu == 1) {
-                a = kk % TX;
-                b = kk / TX;
-                valid = a < ex && b < ez;
-                lo = a + TX * ((emu - 1) + TY * b);
-                li = a + TX * (0 + TY * b);
-            } else {
-                a = kk % TX;
-                b = kk / TX;
-                valid = a < ex && b < ey;
-                lo = a + TX * (b + TY * (emu - 1));
-                li = a + TX * b;
+        for (int m = 0; m < 4; ++m) {
+            const int j = jf + m, rr = r0 + j;
+            if (!row_ok(j)) continue;
+            const int ly = row_y(j), lz = row_z(j);
+            const int32_t rg = (int32_t)gidx(root[j] < 0 ? 0 : root[j]);
+            if (vc) g_label[gat(gx, ly, lz)] = isr[m] ? (ROOT_FLAG | dec[m]) : (uint32_t)rg;
+            // faces for the global merge: the out side marks a bond across the face
+            if (fx) {
+                if (c == ex - 1) fo0[rr] = bit_of(bxg, j) ? rg : -1;
+                if (c == 0) fo0[F0 + rr] = rg;
             }
-            if (!valid) {
-                fo[kk] = -1;
-                fi[kk] = -1;
-                continue;
+            if (fy && vc) {
+                if (ly == ey - 1) fo1[c + TX * lz] = bit_of(byg, j) ? rg : -1;
+                if (ly == 0) fo1[F1 + c + TX * lz] = rg;
             }
-            fo[kk] = ((s_bond[lo] >> mu) & 1u) ? (int32_t)gidx(root_of(lo)) : -1;
-            fi[kk] = (int32_t)gidx(root_of(li));
+            if (DIM == 3 && fz && vc) {
+                if (lz == ez - 1) fo2[c + TX * ly] = bit_of(bzg, j) ? rg : -1;
+                if (lz == 0) fo2[F2 + c + TX * ly] = rg;
+            }
         }
     }
 }
 
 // ---------------------------------------------------------------------------
-// Global label equivalence across tile faces.  grid = (ceil(tiles * FMAX /
-// 256), DIM): thread e of slice mu handles element e % FMAX of the +mu face of
-// tile slot e / FMAX; for every active bond crossing the face it links the
-// larger of the two tile roots under the smaller with device-scope atomicMin.
+// Global label equivalence across tile faces.  One workgroup per tile: for
+// every active bond across one of the tile's +mu faces, the two tile roots
+// are linked on the global label words, the larger under the smaller, with
+// device-scope atomicMin (Hawick's atomicMin on R[label], retried until it
+// links, so one pass reaches the fixed point).  A cluster crosses a face at
+// many sites with the same pair of tile roots: an LDS hash set of the pairs
+// seen lets only the first such bond make the (global, atomic) union.
 // ---------------------------------------------------------------------------
 template <int DIM>
 __global__ void __launch_bounds__(256) k_merge(const InstDesc *__restrict__ descs,
-                                               const int2 *__restrict__ tmap, int ntiles, int fmax,
-                                               uint32_t k)
+                                               const int2 *__restrict__ tmap, uint32_t k)
 {
-    const int mu = blockIdx.y;
-    const int e = tile_slot() * 256 + (int)threadIdx.x;
-    const int ts = e / fmax, kk = e - ts * fmax;
-    if (ts >= ntiles) return;
-    const int2 tm = tmap[ts];
+    constexpr int HB = 2048;  // hash slots
+    constexpr unsigned long long EMPTY = ~0ull;
+    __shared__ unsigned long long s_set[HB];
+    const int2 tm = tmap[tile_slot()];
     if (tm.x < 0) return;
     const InstDesc &d = descs[tm.x];
-    if (k >= d.count || d.tiles[mu] == 1) return;
-    const int F = d.face_len[mu];
-    if (kk >= F) return;
+    if (k >= d.count) return;
     const int t = tm.y;
-    const int32_t a = ((const GLOBAL int32_t *)d.face)[d.face_off[mu] + (int64_t)t * 2 * F + kk];
-    if (a < 0) return;
-    int c[3] = {t % d.tiles[0], (t / d.tiles[0]) % d.tiles[1], (DIM == 3) ? t / (d.tiles[0] * d.tiles[1]) : 0};
-    c[mu] = (c[mu] + 1 == d.tiles[mu]) ? 0 : c[mu] + 1;
-    const int nb = c[0] + d.tiles[0] * (c[1] + d.tiles[1] * c[2]);
-    const int32_t b = ((const GLOBAL int32_t *)d.face)[d.face_off[mu] + (int64_t)nb * 2 * F + F + kk];
-    gunion(d.label, (uint32_t)a, (uint32_t)b);
+    const int tid = threadIdx.x;
+    for (int h = tid; h < HB; h += 256) s_set[h] = EMPTY;
+    __syncthreads();
+    const int tc[3] = {t % d.tiles[0], (t / d.tiles[0]) % d.tiles[1],
+                       (DIM == 3) ? t / (d.tiles[0] * d.tiles[1]) : 0};
+#pragma unroll
+    for (int mu = 0; mu < DIM; ++mu) {
+        if (d.tiles[mu] == 1) continue;
+        const int F = d.face_len[mu];
+        int cn[3] = {tc[0], tc[1], tc[2]};
+        cn[mu] = (cn[mu] + 1 == d.tiles[mu]) ? 0 : cn[mu] + 1;
+        const int nb = cn[0] + d.tiles[0] * (cn[1] + d.tiles[1] * cn[2]);
+        const GLOBAL int32_t *fo = (const GLOBAL int32_t *)d.face + d.face_off[mu] + (int64_t)t * 2 * F;
+        const GLOBAL int32_t *fi = (const GLOBAL int32_t *)d.face + d.face_off[mu] + (int64_t)nb * 2 * F + F;
+        for (int kk = tid; kk < F; kk += 256) {
+            const int32_t a = fo[kk];
+            if (a < 0) continue;
+            const int32_t b = fi[kk];
+            // the previous face element with the same pair makes this union
+            if (kk > 0 && fo[kk - 1] == a && fi[kk - 1] == b) continue;
+            const unsigned long long key = ((unsigned long long)(uint32_t)a << 32) | (uint32_t)b;
+            uint32_t h = ((uint32_t)a * 0x9E3779B1u) ^ ((uint32_t)b * 0x85EBCA77u);
+            bool fresh = true;
+            for (int probe = 0; probe < 8; ++probe) {
+                h = (h + (uint32_t)probe) & (HB - 1);
+                const unsigned long long old = atomicCAS(&s_set[h], EMPTY, key);
+                if (old == EMPTY) break;  // inserted: this thread links the pair
+                if (old == key) {
+                    fresh = false;  // seen before in this tile
+                    break;
+                }
+            }
+            if (fresh) gunion(d.label, (uint32_t)a, (uint32_t)b);
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
 // Reduction of the per-tile measurement partials into one record row, in a
 // fixed order (deterministic, also for the XY sums).  Workgroup t of a
-// lattice reduces slots t, t + ntiles, ... (XY: workgroup 0 all three and
-// rotates the projected sums back by phi).
+// lattice reduces slots t, t + ntiles, ... (XY: workgroup 0 all three).
 // ---------------------------------------------------------------------------
 template <int MODEL>
-__device__ void reduce_partials(const InstDesc &d, int t, uint32_t n, int64_t row)
+__device__ void reduce_partials(const InstDesc &d, int t, int64_t row)
 {
     __shared__ double s_red[4][3];
-    __shared__ double s_phi;
     const int tid = threadIdx.x, wv = tid >> 6, ln = tid & 63;
     GLOBAL int64_t *rec = (GLOBAL int64_t *)d.rec + row * d.nslots;
     const GLOBAL int64_t *part = (const GLOBAL int64_t *)d.part;
     if (MODEL == XY) {
         if (t != 0) return;
-        if (tid == 0) s_phi = xy_phi(d, n);
         double acc[3] = {0.0, 0.0, 0.0};
         for (int tt = tid; tt < d.ntiles; tt += 256)
             for (int c = 0; c < 3; ++c) acc[c] += __longlong_as_double(part[(int64_t)tt * 3 + c]);
@@ -914,12 +941,9 @@ __device__ void reduce_partials(const InstDesc &d, int t, uint32_t n, int64_t ro
         if (tid == 0) {
             double v[3];
             for (int c = 0; c < 3; ++c) v[c] = ((s_red[0][c] + s_red[1][c]) + s_red[2][c]) + s_red[3][c];
-            double sp, cp;
-            sincos(s_phi, &sp, &cp);
-            // sum of (cos, sin)(theta - phi) rotated back by phi
             rec[0] = __double_as_longlong(v[0]);
-            rec[1] = __double_as_longlong(cp * v[1] - sp * v[2]);
-            rec[2] = __double_as_longlong(sp * v[1] + cp * v[2]);
+            rec[1] = __double_as_longlong(v[1]);
+            rec[2] = __double_as_longlong(v[2]);
         }
         __syncthreads();
         return;
@@ -947,27 +971,35 @@ __global__ void __launch_bounds__(256) k_reduce(const InstDesc *__restrict__ des
     if (tm.x < 0) return;
     const InstDesc &d = descs[tm.x];
     if (tm.y >= d.nslots && !(MODEL == XY && tm.y == 0)) return;
-    reduce_partials<MODEL>(d, tm.y, d.sweep0, d.rec_cap);
+    reduce_partials<MODEL>(d, tm.y, d.rec_cap);
 }
 
 // ---------------------------------------------------------------------------
 // (3) every site takes its cluster root's decision.
+//
+// A site's label word is its tile root's global index (or, for a root, ROOT
+// | decision); the merge may have linked tile roots to roots elsewhere.  Lane
+// = column, wavefront w owns rows [w R, (w+1) R) as in k_bond.  All rows'
+// words are loaded first, then all their roots' words, so the dependent
+// loads of a lane overlap; the few chains the merge made longer are walked in
+// lock-step rounds, and the final root is written back into the tile root
+// so that later workgroups take one hop.
 // ---------------------------------------------------------------------------
 template <int MODEL, int DIM, int TX, int TY, int TZ>
 __global__ void __launch_bounds__(256) k_flip(const InstDesc *__restrict__ descs,
                                               const int2 *__restrict__ tmap, uint32_t k)
 {
-    constexpr int T = TX * TY * TZ;
-    constexpr int QX = TX / 4;
-    constexpr int NQ = T / 4;
-    constexpr int QPT = (NQ + 255) / 256;
+    constexpr int ROWS = TY * TZ;
+    constexpr int R = ROWS / 4;
+    static_assert(TX == 64 && ROWS % 4 == 0, "lane = column, whole rows per wavefront");
     __shared__ double s_phi;
     const int2 tm = tmap[tile_slot()];
     if (tm.x < 0) return;
-    const InstDesc &d = descs[tm.x];
+    const InstDesc d = descs[tm.x];
     if (k >= d.count) return;
     const uint32_t n = d.sweep0 + k;
     const int L = d.L;
+    const uint32_t uL = (uint32_t)L;
     const int t = tm.y;
     const int tx = t % d.tiles[0];
     const int ty = (t / d.tiles[0]) % d.tiles[1];
@@ -975,81 +1007,73 @@ __global__ void __launch_bounds__(256) k_flip(const InstDesc *__restrict__ descs
     const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
     const int ex = min(TX, L - x0), ey = min(TY, L - y0), ez = (DIM == 3) ? min(TZ, L - z0) : 1;
     const int tid = threadIdx.x;
+    const int c = tid & 63, wv = tid >> 6;
+    const int r0 = wv * R;
+    const bool vc = c < ex;
     // the first workgroups of a lattice also reduce the sweep's measurement
     if (d.measure && d.rec_row0 >= 0 && d.rec_row0 + (int64_t)k < d.rec_cap &&
         (t < d.nslots || (MODEL == XY && t == 0)))
-        reduce_partials<MODEL>(d, t, n, d.rec_row0 + (int64_t)k);
+        reduce_partials<MODEL>(d, t, d.rec_row0 + (int64_t)k);
     if (MODEL == XY) {
         if (tid == 0) s_phi = xy_phi(d, n);
         __syncthreads();
     }
+    GLOBAL uint32_t *g_label = (GLOBAL uint32_t *)d.label;
+    auto row_ok = [&](int j) -> bool {
+        const int rr = r0 + j;
+        return (rr % TY) < ey && (rr / TY) < ez;
+    };
+    auto gsite = [&](int j) -> uint32_t {
+        const int rr = r0 + j;
+        return (uint32_t)(x0 + c) + uL * ((uint32_t)(y0 + rr % TY) + uL * (uint32_t)(z0 + rr / TY));
+    };
+
+    // rows in two batches (fewer registers), the loads of a batch in flight together
+    constexpr int RH = (R >= 8) ? R / 2 : R;
     const double phi = (MODEL == XY) ? s_phi : 0.0;
-    uint32_t *lab = d.label;
+#pragma unroll 1
+    for (int h = 0; h < R; h += RH) {
+        uint32_t w[RH], cur[RH], val[RH];
 #pragma unroll
-    for (int j = 0; j < QPT; ++j) {
-        const int qid = tid + 256 * j;
-        if (qid >= NQ) continue;
-        const int qx = qid % QX, row = qid / QX;
-        const int ly = row % TY, lz = row / TY;
-        const int lx0 = qx * 4;
-        if (ly >= ey || lz >= ez || lx0 >= ex) continue;
-        const int nv = min(4, ex - lx0);
-        const uint32_t gi0 = (uint32_t)(x0 + lx0) +
-                             (uint32_t)L * ((uint32_t)(y0 + ly) + (uint32_t)L * (uint32_t)(z0 + lz));
-        const bool vec = ((gi0 & 3u) == 0) && nv == 4;
-        uint32_t v[4];
-        if (vec) {
-            const uint4 q4 = *(const uint4 *)(lab + gi0);
-            v[0] = q4.x;
-            v[1] = q4.y;
-            v[2] = q4.z;
-            v[3] = q4.w;
-        } else {
-            for (int m = 0; m < 4; ++m) v[m] = (m < nv) ? lab[gi0 + m] : ROOT_FLAG;
+        for (int i = 0; i < RH; ++i) {
+            w[i] = ROOT_FLAG;
+            if (vc && row_ok(h + i)) w[i] = g_label[gsite(h + i)];
         }
-        uint32_t dec[4];
+        // cur: the tile root (or the site itself); val: its word
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            uint32_t x = v[m];
-            if (!(x & ROOT_FLAG)) {
-                // x is the tile-local root; follow the links the merge made and
-                // point x straight at the final root for the sites after us
-                const uint32_t r = x;
-                uint32_t g = r;
-                x = lab[r];
-                if (!(x & ROOT_FLAG)) {
-                    while (!(x & ROOT_FLAG)) {
-                        g = x;
-                        x = lab[g];
-                    }
-                    if (lab[r] != g) lab[r] = g;
+        for (int i = 0; i < RH; ++i) {
+            cur[i] = w[i];
+            val[i] = (w[i] & ROOT_FLAG) ? w[i] : g_label[w[i]];
+        }
+        // chains the merge made longer, walked in lock-step rounds
+        bool more = false;
+#pragma unroll
+        for (int i = 0; i < RH; ++i) more |= !(val[i] & ROOT_FLAG);
+        while (__any(more)) {
+            more = false;
+#pragma unroll
+            for (int i = 0; i < RH; ++i) {
+                if (!(val[i] & ROOT_FLAG)) {
+                    cur[i] = val[i];
+                    val[i] = g_label[cur[i]];
+                    more |= !(val[i] & ROOT_FLAG);
                 }
             }
-            dec[m] = x & 0xffu;
         }
-        if (MODEL == ISING || MODEL == POTTS) {
-            uint32_t packed = 0;
-            for (int m = 0; m < 4; ++m) {
-                const uint32_t s = (MODEL == ISING) ? (dec[m] ? 0xffu : 0x01u) : dec[m];
-                packed |= s << (8 * m);
-            }
-            if (vec) {
-                *(uint32_t *)((uint8_t *)d.state + gi0) = packed;
-            } else {
-                for (int m = 0; m < nv; ++m) ((uint8_t *)d.state)[gi0 + m] = (uint8_t)(packed >> (8 * m));
-            }
-        } else {
-            float *th = (float *)d.state;
-            if (vec) {
-                float4 a = *(const float4 *)(th + gi0);
-                if (dec[0]) a.x = xy_reflect(a.x, phi);
-                if (dec[1]) a.y = xy_reflect(a.y, phi);
-                if (dec[2]) a.z = xy_reflect(a.z, phi);
-                if (dec[3]) a.w = xy_reflect(a.w, phi);
-                *(float4 *)(th + gi0) = a;
-            } else {
-                for (int m = 0; m < nv; ++m)
-                    if (dec[m]) th[gi0 + m] = xy_reflect(th[gi0 + m], phi);
+#pragma unroll
+        for (int i = 0; i < RH; ++i) {
+            // point the tile root straight at the final root
+            if (!(w[i] & ROOT_FLAG) && cur[i] != w[i]) g_label[w[i]] = cur[i];
+            if (!vc || !row_ok(h + i)) continue;
+            const uint32_t dec = val[i] & 0xffu;
+            const uint32_t g = gsite(h + i);
+            if (MODEL == ISING) {
+                ((GLOBAL int8_t *)d.state)[g] = dec ? (int8_t)-1 : (int8_t)1;
+            } else if (MODEL == POTTS) {
+                ((GLOBAL uint8_t *)d.state)[g] = (uint8_t)dec;
+            } else if (dec) {
+                GLOBAL float *th = (GLOBAL float *)d.state;
+                th[g] = xy_reflect(th[g], phi);
             }
         }
     }
@@ -1165,16 +1189,11 @@ hipError_t launch_bond(int model, int dim, int v, const InstDesc *dd, const int2
 hipError_t launch_merge(int dim, int model, int v, const InstDesc *dd, const int2 *tm, int nt, uint32_t k,
                         hipStream_t s)
 {
+    (void)model;
+    (void)v;
     if (nt <= 0) return hipSuccess;
-    const TileShape ts = tile_shape(model, dim, v);
-    const int ext[3] = {ts.tx, ts.ty, dim == 3 ? ts.tz : 1};
-    const int T = ext[0] * ext[1] * ext[2];
-    int fmax = 0;
-    for (int mu = 0; mu < dim; ++mu) fmax = T / ext[mu] > fmax ? T / ext[mu] : fmax;
-    const long long blocks = ((long long)nt * fmax + 255) / 256;
-    const dim3 grid((unsigned)blocks, dim);
-    if (dim == 2) hipLaunchKernelGGL((k_merge<2>), grid, dim3(256), 0, s, dd, tm, nt, fmax, k);
-    else hipLaunchKernelGGL((k_merge<3>), grid, dim3(256), 0, s, dd, tm, nt, fmax, k);
+    if (dim == 2) hipLaunchKernelGGL((k_merge<2>), dim3(nt), dim3(256), 0, s, dd, tm, k);
+    else hipLaunchKernelGGL((k_merge<3>), dim3(nt), dim3(256), 0, s, dd, tm, k);
     return hipGetLastError();
 }
 

@@ -81,3 +81,20 @@ def test_bench_refuses_several_gpus():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_tile_shapes_are_host_logic():
+    import paper_1403_7560_amd as sw
+    for model in (sw.ISING, sw.POTTS, sw.XY):
+        for dim in (2, 3):
+            n = sw.tile_count(model, dim)
+            assert n >= 1
+            for t in range(n):
+                tx, ty, tz = sw.tile_shape(model, dim, t)
+                assert tx == 64 and ty % 4 == 0 and (tz == 1 if dim == 2 else tz >= 1)
+                assert tx * ty * tz <= 8192
+            with pytest.raises(sw.SWError):
+                sw.tile_shape(model, dim, n)
+    assert sw.tile_shape(sw.ISING, 2, 0) == (64, 64, 1)
+    with pytest.raises(sw.SWError):
+        sw.tile_count(3, 2)

@@ -6,9 +6,10 @@ angles within 1e-5 rad (circular distance); the FP64 bond test and the mirror
 are evaluated in the same order on both sides, so they are expected to agree
 bit for bit as well.
 
-Sizes span several tiles with a ragged tail (tiles are 128x32 / 64x32 in 2D
-and 32x16x8 / 16x16x8 in 3D) plus lattices smaller than one tile, where the
-periodic wrap stays inside the tile.
+Sizes span several tiles with a ragged tail (the default tiles are 64x64
+(Ising/Potts) and 64x32 (XY) in 2D, 64x8x8 and 64x4x8 in 3D) plus lattices
+smaller than one tile, where the periodic wrap stays inside the tile; every
+other tile shape runs on ragged lattices too.
 """
 import math
 import sys
@@ -101,6 +102,43 @@ def test_hot_start_and_sweeps(model, dim, L, q, T, n):
     compare_records(model, dim, L, q, lat.series(), ref["records"])
     assert lat.sweep_index() == n
     lat.close()
+
+
+TILE_CASES = [(ISING, 2, 150, 2, 2.269185), (POTTS, 2, 99, 4, 0.91), (ISING, 3, 21, 2, 4.5115),
+              (POTTS, 3, 17, 3, 1.8), (XY, 2, 70, 0, 0.9), (XY, 3, 19, 0, 2.2019)]
+
+
+@pytest.mark.parametrize("model,dim,L,q,T", TILE_CASES)
+def test_every_tile_shape(model, dim, L, q, T):
+    """The tile shape changes the launch, never the trajectory."""
+    n, seed, beta = 4, 31 + L, 1.0 / T
+    s0 = oracle.init_state(model, dim, L, q, seed)
+    ref = oracle.sweeps(model, dim, L, q, beta, seed, 0, 0, n, s0)
+    for tile in range(sw.tile_count(model, dim)):
+        say(f"[tile] model={model} dim={dim} L={L} tile={tile} {sw.tile_shape(model, dim, tile)}")
+        lat = sw.Lattice(model, dim, L, q, beta, seed, tile=tile)
+        assert lat.tile == tile
+        lat.sweep(n)
+        compare_lattice(model, lat.get_state(), lat.get_labels(), lat.get_bonds(), ref)
+        compare_records(model, dim, L, q, lat.series(), ref["records"])
+        lat.close()
+
+
+def test_tuner_picks_a_shape_used_by_later_lattices():
+    say("[tune] Ising 2D L=200")
+    best, ms = sw.tune(ISING, 2, 200, 2, 0.44, sweeps=3)
+    assert 0 <= best < sw.tile_count(ISING, 2)
+    assert len(ms) == sw.tile_count(ISING, 2) and all(m > 0 for m in ms)
+    assert ms[best] == min(ms)
+    lat = sw.Lattice(ISING, 2, 200, 2, 0.44, 5)
+    assert lat.tile == best
+    lat.sweep(3)
+    ref = oracle.sweeps(ISING, 2, 200, 2, 0.44, 5, 0, 0, 3, oracle.init_state(ISING, 2, 200, 2, 5))
+    compare_lattice(ISING, lat.get_state(), lat.get_labels(), lat.get_bonds(), ref)
+    b = sw.Batch([dict(model=ISING, dim=2, L=200, q=2, beta=0.44, seed=5, replica=0)])
+    assert b.members[0].tile == best
+    with pytest.raises(sw.SWError):
+        sw.Lattice(ISING, 2, 64, 2, 0.44, 1, tile=sw.tile_count(ISING, 2))
 
 
 @pytest.mark.parametrize("model,dim,L,q,T", [(ISING, 2, 100, 2, 2.3), (POTTS, 3, 20, 5, 1.0),
