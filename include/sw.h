@@ -142,12 +142,14 @@ void sw_destroy(sw_handle h);
 /* Message of the last error on the calling thread ("" if none). */
 const char *sw_last_error(void);
 
-/* Per-kernel device time.  While on, every launch of the three sweep
- * kernels (0 = bond generation + tile labelling, 1 = label merge across
- * tiles, 2 = cluster flip) is bracketed by HIP events on the handle's stream
- * and its duration accumulated.  sw_profile(h, 1) also clears the totals. */
+/* Per-kernel device time.  Level 1 brackets every launch of the bond kernel
+ * (bond generation + tile labelling) with HIP events on the handle's stream
+ * and accumulates its duration; level 2 also times the label merge across
+ * tiles and the cluster flip (more events, so a little slower); 0 turns it
+ * off.  Any level > 0 clears the totals.  SW_E_INVALID for other levels. */
 int sw_profile(sw_handle h, int on);
-/* Accumulated milliseconds and launch counts per kernel (3 entries each). */
+/* Accumulated milliseconds and launch counts per kernel (3 entries each:
+ * 0 = bond, 1 = merge, 2 = flip; untimed kernels stay 0). */
 int sw_profile_read(sw_handle h, double *ms, int64_t *launches);
 
 /* --- state access (checkpoint / parity hooks) ----------------------------- */

@@ -192,8 +192,9 @@ class Lattice:
                for k in ("sweep", "energy", "mag", "mag2", "mx", "my")}
         return out
 
-    def profile(self, on):
-        _check(lib().sw_profile(self.h, 1 if on else 0))
+    def profile(self, level):
+        """0 off; 1 time every bond-kernel launch; 2 time all three kernels."""
+        _check(lib().sw_profile(self.h, int(level)))
 
     def profile_read(self):
         ms = np.zeros(3)

@@ -104,7 +104,7 @@ struct Lattice {
     int2 *d_tmap = nullptr;      // tile map for solo sweeps
     hipStream_t stream = nullptr;
     // per-kernel event timing
-    bool profiling = false;
+    int profiling = 0;  // 1: events around k_bond; 2: around all three kernels
     std::vector<hipEvent_t> events;
     double prof_ms[3] = {0, 0, 0};
     int64_t prof_n[3] = {0, 0, 0};
@@ -294,14 +294,15 @@ struct Lattice {
                 HIPCHK(launch_bond(model, dim, variant, d_solo, d_tmap, ntiles, (uint32_t)k, 0, stream));
                 if (ev) HIPCHK(hipEventRecord(ev[1], stream));
                 HIPCHK(launch_merge(dim, model, variant, d_solo, d_tmap, ntiles, (uint32_t)k, stream));
-                if (ev) HIPCHK(hipEventRecord(ev[2], stream));
+                if (ev && profiling > 1) HIPCHK(hipEventRecord(ev[2], stream));
                 HIPCHK(launch_flip(model, dim, variant, d_solo, d_tmap, ntiles, (uint32_t)k, stream));
-                if (ev) HIPCHK(hipEventRecord(ev[3], stream));
+                if (ev && profiling > 1) HIPCHK(hipEventRecord(ev[3], stream));
             }
             HIPCHK(hipStreamSynchronize(stream));
             if (profiling) {
+                const int nk = profiling > 1 ? 3 : 1;
                 for (int64_t k = 0; k < m; ++k) {
-                    for (int c = 0; c < 3; ++c) {
+                    for (int c = 0; c < nk; ++c) {
                         float ms = 0.f;
                         HIPCHK(hipEventElapsedTime(&ms, events[(size_t)(4 * k + c)], events[(size_t)(4 * k + c + 1)]));
                         prof_ms[c] += ms;
@@ -956,7 +957,8 @@ int sw_set_measure(sw_handle h, int on)
 int sw_profile(sw_handle h, int on)
 {
     CHECK_H(h);
-    h->lat->profiling = on != 0;
+    if (on < 0 || on > 2) return fail(SW_E_INVALID, "profiling level must be 0, 1 or 2");
+    h->lat->profiling = on;
     if (on)
         for (int c = 0; c < 3; ++c) {
             h->lat->prof_ms[c] = 0.0;

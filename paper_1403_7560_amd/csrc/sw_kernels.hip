@@ -103,10 +103,15 @@ __device__ __forceinline__ double wave_sum_d(double v)
 }
 
 // ---- union-find in LDS (tile-local indices) --------------------------------
+// The parent table is addressed through an LDS (address space 3) pointer so
+// that every access is a ds_* instruction.  Loads are volatile: other lanes
+// and wavefronts link roots concurrently.
+typedef __attribute__((address_space(3))) int lds_int;
+
 // Root of a with path halving: a non-root's parent may be replaced by any
 // ancestor (every pointer goes to a smaller index of the same cluster), so
 // the plain store is safe against concurrent unions.
-__device__ __forceinline__ int lds_find(volatile int *par, int a)
+__device__ __forceinline__ int lds_find(volatile lds_int *par, int a)
 {
     while (true) {
         const int p = par[a];
@@ -118,9 +123,9 @@ __device__ __forceinline__ int lds_find(volatile int *par, int a)
     }
 }
 
-__device__ __forceinline__ void lds_union(int *par, int a, int b)
+__device__ __forceinline__ void lds_union(lds_int *par, int a, int b)
 {
-    volatile int *vp = par;
+    volatile lds_int *vp = par;
     while (true) {
         a = lds_find(vp, a);
         b = lds_find(vp, b);
@@ -130,9 +135,20 @@ __device__ __forceinline__ void lds_union(int *par, int a, int b)
             a = b;
             b = t;
         }
-        const int old = atomicMin(&par[a], b);
+        const int old = __hip_atomic_fetch_min(&par[a], b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         if (old == a) return;  // a was still a root: now linked under b
         a = old;               // a was linked meanwhile: merge its parent instead
+    }
+}
+
+// Apply a wavefront's queued equivalences (a << 16 | b) to the LDS table;
+// called with the whole wavefront, lane l takes entries l, l + 64, ...
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
+__device__ __noinline__ void flush_queue(lds_int *par, const lds_u32 *q, int qn, int lane)
+{
+    for (int e = lane; e < qn; e += 64) {
+        const uint32_t pr = q[e];
+        lds_union(par, (int)(pr >> 16), (int)(pr & 0xffffu));
     }
 }
 
@@ -265,6 +281,27 @@ __device__ __noinline__ uint32_t bond_secondary(uint32_t key0, uint32_t key1, ui
     return lane_of(b, w & 3u) >> 16;
 }
 
+// (cos theta, sin theta) in FP64 for a float angle in [0, 2pi], from a table
+// of cos/sin(k 2pi/128) and short polynomials in r = theta - k 2pi/128,
+// |r| <= pi/128: the truncated Taylor terms are below 1e-20 and the rounding
+// a few ulps, ample for the measurement sums and the fast bond test (the
+// exact bond test uses the library cos).
+#define XY_TAB 128
+__device__ __forceinline__ void xy_sincos(float th, const double2 *tab, double &c, double &s)
+{
+    const double DHI = TWO_PI_D / XY_TAB;                   // exact: 2pi_d / 2^7
+    const double DLO = 2.4492935982947064e-16 / XY_TAB;     // 2pi - 2pi_d, scaled
+    const int k = (int)((float)th * (float)(XY_TAB / TWO_PI_D) + 0.5f);
+    double r = fma(-(double)k, DHI, (double)th);
+    r = fma(-(double)k, DLO, r);
+    const double r2 = r * r;
+    const double cr = fma(r2, fma(r2, fma(r2, fma(r2, 1.0 / 40320.0, -1.0 / 720.0), 1.0 / 24.0), -0.5), 1.0);
+    const double sr = r * fma(r2, fma(r2, fma(r2, fma(r2, 1.0 / 362880.0, -1.0 / 5040.0), 1.0 / 120.0), -1.0 / 6.0), 1.0);
+    const double2 t = tab[k & (XY_TAB - 1)];
+    c = fma(t.x, cr, -(t.y * sr));
+    s = fma(t.y, cr, t.x * sr);
+}
+
 // XY bond test, exact form: u = (P 2^16 + S) 2^-32 < -expm1(-(2 beta s_i) s_j)
 // with s = cos(theta - phi) in FP64, decided from the 16-bit primary alone
 // unless u's interval straddles p.  The angles are re-read from HBM: this
@@ -328,7 +365,7 @@ template <> struct LaneValue<XY> { typedef double type; };
 // many as its LDS allows (160 KB per CU), up to the 8 waves per SIMD of the
 // hardware; XY keeps its FP64 projections in registers and runs 4.
 template <int MODEL, int T> struct BondOccupancy {
-    static constexpr int value = (MODEL == XY) ? 4 : ((T <= 2048) ? 8 : ((T <= 4096) ? 7 : 3));
+    static constexpr int value = (MODEL == XY) ? 4 : ((T <= 4096) ? 8 : 3);
 };
 
 template <int MODEL, int DIM, int TX, int TY, int TZ>
@@ -351,11 +388,16 @@ k_bond(const InstDesc *__restrict__ descs,
 
     __shared__ int s_par[T];
     __shared__ unsigned long long s_xm[ROWS];  // in-tile x-bond mask of every row
-    __shared__ uint32_t s_cw[ROWS * 8];        // cluster decision words, 8 per tile row
+    __shared__ uint32_t s_rowg[ROWS];          // global index of every row's first site
+    __shared__ uint32_t s_cw[ROWS * 3];        // cluster decision words, 3 per tile row
     __shared__ uint32_t s_q[4][QCAP];
-    __shared__ int s_hist[MODEL == POTTS ? 256 : 1];
+    // Potts histogram of the measurement: it is done before the scan fills the
+    // equivalence queues, so it shares their memory
+    int *s_hist = (int *)&s_q[0][0];
+    static_assert(4 * QCAP >= 256, "histogram fits the queues");
     __shared__ double s_red[4][3];
     __shared__ double s_phi[3];  // XY: phi, cos phi, sin phi
+    __shared__ double2 s_cs[IS_XY ? XY_TAB : 1];  // XY: cos/sin(k 2pi/128)
 
     const int2 tm = tmap[tile_slot()];
     if (tm.x < 0) return;
@@ -370,7 +412,9 @@ k_bond(const InstDesc *__restrict__ descs,
     const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
     const int ex = min(TX, L - x0), ey = min(TY, L - y0), ez = (DIM == 3) ? min(TZ, L - z0) : 1;
     const int tid = threadIdx.x;
-    const int c = tid & 63, wv = tid >> 6;
+    // the wavefront index is uniform: readfirstlane lets everything derived
+    // from it (rows, global addresses) live in scalar registers
+    const int c = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int r0 = wv * R;
     const bool vc = c < ex;
     const bool full = (mode == 0);
@@ -396,10 +440,14 @@ k_bond(const InstDesc *__restrict__ descs,
         return x + uL * (y + uL * z);
     };
     auto gidx = [&](int l) -> uint32_t {  // tile-local index -> global index
-        const int row = l >> 6;
-        return (uint32_t)(x0 + (l & 63)) + uL * ((uint32_t)(y0 + row % TY) + uL * (uint32_t)(z0 + row / TY));
+        return s_rowg[l >> 6] + (uint32_t)(l & 63);
     };
 
+    if (IS_XY && tid < XY_TAB) {
+        double sk, ck;
+        sincos((double)tid * (TWO_PI_D / XY_TAB), &sk, &ck);
+        s_cs[tid] = make_double2(ck, sk);
+    }
     if (IS_XY && tid == 0) {
         const double ph = xy_phi(d, n);
         double sp, cp;
@@ -410,16 +458,23 @@ k_bond(const InstDesc *__restrict__ descs,
     }
     if (MODEL == POTTS && meas)
         for (int q = tid; q < d.q; q += 256) s_hist[q] = 0;
+    for (int r = tid; r < ROWS; r += 256) s_rowg[r] = gat((uint32_t)x0, r % TY, r / TY);
     // Cluster decision words of every tile row (one bit per possible root):
-    // row r needs words g/32 for its sites g, which lie in Philox blocks
-    // g_r/128 and g_r/128 + 1 of the cluster stream.
+    // the sites g_r .. g_r + 63 of row r use words g_r/32 .. g_r/32 + 2,
+    // which lie in Philox blocks g_r/128 and g_r/128 + 1 of the cluster stream.
     if (full && bits_dec && tid < 2 * ROWS) {
         const int r = tid >> 1, half = tid & 1;
         const int ly = r % TY, lz = r / TY;
         if (ly < ey && lz < ez) {
             const uint32_t gr = gat((uint32_t)x0, ly, lz);
-            const uint4 w = philox(make_uint4((gr >> 7) + (uint32_t)half, n, (uint32_t)TAG_CLUSTER, rep), key0, key1);
-            *(uint4 *)&s_cw[8 * r + 4 * half] = w;
+            const uint32_t blk = (gr >> 7) + (uint32_t)half;
+            const uint4 w = philox(make_uint4(blk, n, (uint32_t)TAG_CLUSTER, rep), key0, key1);
+            const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const uint32_t kk = 4 * blk + (uint32_t)i - (gr >> 5);
+                if (kk < 3u) s_cw[3 * r + (int)kk] = ws[i];
+            }
         }
     }
     if (IS_XY || (MODEL == POTTS && meas)) __syncthreads();
@@ -432,7 +487,7 @@ k_bond(const InstDesc *__restrict__ descs,
     auto value_at = [&](uint32_t g, V &vs) -> V {
         if constexpr (IS_XY) {
             double sv, cv;
-            sincos((double)((const GLOBAL float *)d.state)[g], &sv, &cv);
+            xy_sincos(((const GLOBAL float *)d.state)[g], s_cs, cv, sv);
             vs = sv;
             return cv;
         } else {
@@ -705,10 +760,7 @@ k_bond(const InstDesc *__restrict__ descs,
     const unsigned long long from = ~((1ull << c) - 1ull);
     int qn = 0;  // entries in this wave's queue (uniform)
     auto flush = [&]() {
-        for (int e = c; e < qn; e += 64) {
-            const uint32_t pr = s_q[wv][e];
-            lds_union(s_par, (int)(pr >> 16), (int)(pr & 0xffffu));
-        }
+        if (qn) flush_queue((lds_int *)s_par, (const lds_u32 *)s_q[wv], qn, c);
         qn = 0;
     };
     auto push = [&](bool want, int a, int b) {
@@ -744,7 +796,7 @@ k_bond(const InstDesc *__restrict__ descs,
             const unsigned long long conn = __ballot(cand != NONE);
             const unsigned long long mr = conn >> rs;
             const int f = mr ? rs + __ffsll((long long)mr) - 1 : 64;
-            const int fl = __shfl(cand, f & 63, 64);
+            const int fl = __builtin_amdgcn_ds_bpermute((f & 63) << 2, cand);
             const int node = rs + TX * rr;
             const int lab = (f <= re) ? fl : node;
             if (vc && c == rs) s_par[node] = lab;
@@ -824,8 +876,8 @@ k_bond(const InstDesc *__restrict__ descs,
                 const int j = jf + m, rr = r0 + j;
                 if (!isr[m]) continue;
                 const uint32_t g = gat(gx, row_y(j), row_z(j));
-                const uint32_t base = (gat((uint32_t)x0, row_y(j), row_z(j)) >> 7) << 2;
-                dec[m] = (s_cw[8 * rr + (int)((g >> 5) - base)] >> (g & 31u)) & 1u;
+                const uint32_t base = gat((uint32_t)x0, row_y(j), row_z(j)) >> 5;
+                dec[m] = (s_cw[3 * rr + (int)((g >> 5) - base)] >> (g & 31u)) & 1u;
             }
         } else if (__ballot(isr[0] || isr[1] || isr[2] || isr[3])) {
             const uint32_t gyf = (uint32_t)(y0 + row_y(jf)), gzf = (uint32_t)(z0 + row_z(jf));
@@ -871,7 +923,7 @@ template <int DIM>
 __global__ void __launch_bounds__(256) k_merge(const InstDesc *__restrict__ descs,
                                                const int2 *__restrict__ tmap, uint32_t k)
 {
-    constexpr int HB = 2048;  // hash slots
+    constexpr int HB = (DIM == 2) ? 256 : 2048;  // hash slots (about 2x the face elements)
     constexpr unsigned long long EMPTY = ~0ull;
     __shared__ unsigned long long s_set[HB];
     const int2 tm = tmap[tile_slot()];
@@ -986,7 +1038,7 @@ __global__ void __launch_bounds__(256) k_reduce(const InstDesc *__restrict__ des
 // so that later workgroups take one hop.
 // ---------------------------------------------------------------------------
 template <int MODEL, int DIM, int TX, int TY, int TZ>
-__global__ void __launch_bounds__(256) k_flip(const InstDesc *__restrict__ descs,
+__global__ void __launch_bounds__(256, 8) k_flip(const InstDesc *__restrict__ descs,
                                               const int2 *__restrict__ tmap, uint32_t k)
 {
     constexpr int ROWS = TY * TZ;
@@ -1007,7 +1059,9 @@ __global__ void __launch_bounds__(256) k_flip(const InstDesc *__restrict__ descs
     const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
     const int ex = min(TX, L - x0), ey = min(TY, L - y0), ez = (DIM == 3) ? min(TZ, L - z0) : 1;
     const int tid = threadIdx.x;
-    const int c = tid & 63, wv = tid >> 6;
+    // the wavefront index is uniform: readfirstlane lets everything derived
+    // from it (rows, global addresses) live in scalar registers
+    const int c = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int r0 = wv * R;
     const bool vc = c < ex;
     // the first workgroups of a lattice also reduce the sweep's measurement
@@ -1028,8 +1082,9 @@ __global__ void __launch_bounds__(256) k_flip(const InstDesc *__restrict__ descs
         return (uint32_t)(x0 + c) + uL * ((uint32_t)(y0 + rr % TY) + uL * (uint32_t)(z0 + rr / TY));
     };
 
-    // rows in two batches (fewer registers), the loads of a batch in flight together
-    constexpr int RH = (R >= 8) ? R / 2 : R;
+    // the rows' loads in flight together, in two batches from 16 rows per
+    // wavefront on (registers for 8 wavefronts per SIMD)
+    constexpr int RH = (R >= 16) ? R / 2 : R;
     const double phi = (MODEL == XY) ? s_phi : 0.0;
 #pragma unroll 1
     for (int h = 0; h < R; h += RH) {
