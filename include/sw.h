@@ -143,13 +143,14 @@ void sw_destroy(sw_handle h);
 const char *sw_last_error(void);
 
 /* Per-kernel device time.  Level 1 brackets every launch of the bond kernel
- * (bond generation + tile labelling) with HIP events on the handle's stream
+ * (bond generation + tile labelling; for Ising and Potts it also applies the
+ * previous sweep's cluster decisions) with HIP events on the handle's stream
  * and accumulates its duration; level 2 also times the label merge across
- * tiles and the cluster flip (more events, so a little slower); 0 turns it
- * off.  Any level > 0 clears the totals.  SW_E_INVALID for other levels. */
+ * tiles (more events, so a little slower); 0 turns it off.  Any level > 0
+ * clears the totals.  SW_E_INVALID for other levels. */
 int sw_profile(sw_handle h, int on);
 /* Accumulated milliseconds and launch counts per kernel (3 entries each:
- * 0 = bond, 1 = merge, 2 = flip; untimed kernels stay 0). */
+ * 0 = bond, 1 = merge, 2 = flip; the flip is not timed and stays 0). */
 int sw_profile_read(sw_handle h, double *ms, int64_t *launches);
 
 /* --- state access (checkpoint / parity hooks) ----------------------------- */

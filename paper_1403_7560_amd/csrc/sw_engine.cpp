@@ -93,7 +93,8 @@ struct Lattice {
     bool store_bonds = true;
     bool swept = false;
     void *state = nullptr;
-    uint32_t *label = nullptr;
+    uint32_t *label = nullptr;   // label words of even sweeps
+    uint32_t *label2 = nullptr;  // label words of odd sweeps
     uint8_t *bond = nullptr;
     int32_t *face = nullptr;
     int64_t *part = nullptr;
@@ -127,11 +128,12 @@ struct Lattice {
 
     void release()
     {
-        void *ptrs[] = {state, label, bond, face, part, rec, d_solo, d_tmap};
+        void *ptrs[] = {state, label, label2, bond, face, part, rec, d_solo, d_tmap};
         for (void *p : ptrs)
             if (p) (void)hipFree(p);
         state = nullptr;
         label = nullptr;
+        label2 = nullptr;
         bond = nullptr;
         face = nullptr;
         part = nullptr;
@@ -153,7 +155,7 @@ struct Lattice {
         for (int mu = 0; mu < dim; ++mu)
             if (t[mu] > 1) face += nt * 2 * (T / ext[mu]) * 4;
         const int ns = slots_for(model, q);
-        return N * (int64_t)state_bytes(model) + N * 4 + N + face + nt * ns * 8 + 1025 * ns * 8 +
+        return N * (int64_t)state_bytes(model) + 2 * N * 4 + N + face + nt * ns * 8 + 1025 * ns * 8 +
                (int64_t)sizeof(InstDesc) + nt * 8;
     }
 
@@ -186,6 +188,7 @@ struct Lattice {
         d.rec_cap = rec_cap;
         d.state = state;
         d.label = label;
+        d.label2 = label2;
         d.bond = bond;
         d.face = face;
         for (int k = 0; k < 3; ++k) {
@@ -244,7 +247,8 @@ struct Lattice {
             if (mu < dim && tiles[mu] > 1) face_total += (int64_t)ntiles * 2 * face_len[mu];
         }
         if (hipMalloc(&state, (size_t)N * state_bytes(model)) != hipSuccess ||
-            hipMalloc(&label, (size_t)N * 4) != hipSuccess || hipMalloc(&bond, (size_t)N) != hipSuccess ||
+            hipMalloc(&label, (size_t)N * 4) != hipSuccess || hipMalloc(&label2, (size_t)N * 4) != hipSuccess ||
+            hipMalloc(&bond, (size_t)N) != hipSuccess ||
             hipMalloc(&face, (size_t)std::max<int64_t>(face_total, 1) * 4) != hipSuccess ||
             hipMalloc(&part, (size_t)ntiles * nslots * 8) != hipSuccess ||
             hipMalloc(&d_solo, sizeof(InstDesc)) != hipSuccess ||
@@ -288,6 +292,10 @@ struct Lattice {
                 int rc = ensure_events((size_t)(4 * m));
                 if (rc) return rc;
             }
+            // Ising / Potts: each sweep's bond kernel applies the previous
+            // sweep's cluster decisions; the chain's last decisions are applied
+            // once at the end.  XY flips every sweep (the mirror needs the old
+            // angle).
             for (int64_t k = 0; k < m; ++k) {
                 hipEvent_t *ev = profiling ? &events[(size_t)(4 * k)] : nullptr;
                 if (ev) HIPCHK(hipEventRecord(ev[0], stream));
@@ -295,12 +303,12 @@ struct Lattice {
                 if (ev) HIPCHK(hipEventRecord(ev[1], stream));
                 HIPCHK(launch_merge(dim, model, variant, d_solo, d_tmap, ntiles, (uint32_t)k, stream));
                 if (ev && profiling > 1) HIPCHK(hipEventRecord(ev[2], stream));
-                HIPCHK(launch_flip(model, dim, variant, d_solo, d_tmap, ntiles, (uint32_t)k, stream));
-                if (ev && profiling > 1) HIPCHK(hipEventRecord(ev[3], stream));
+                if (model == XY) HIPCHK(launch_flip(model, dim, variant, d_solo, d_tmap, ntiles, (uint32_t)k, stream));
             }
+            if (model != XY) HIPCHK(launch_flip(model, dim, variant, d_solo, d_tmap, ntiles, FLIP_LAST, stream));
             HIPCHK(hipStreamSynchronize(stream));
             if (profiling) {
-                const int nk = profiling > 1 ? 3 : 1;
+                const int nk = profiling > 1 ? 2 : 1;
                 for (int64_t k = 0; k < m; ++k) {
                     for (int c = 0; c < nk; ++c) {
                         float ms = 0.f;
@@ -388,7 +396,10 @@ struct Lattice {
             return fail(SW_E_NOMEM, "cluster statistics scratch allocation failed");
         }
         unsigned long long h[3] = {0, 0, 0};
-        hipError_t e = hipMemcpyAsync(out, h, 24, hipMemcpyHostToDevice, stream);
+        // a current descriptor: its sweep index names the last sweep's label buffer
+        InstDesc d = desc();
+        hipError_t e = hipMemcpyAsync(d_solo, &d, sizeof(d), hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(out, h, 24, hipMemcpyHostToDevice, stream);
         if (e == hipSuccess) e = launch_cluster_stats(d_solo, 0, N, scratch, out, stream);
         if (e == hipSuccess) e = hipMemcpyAsync(h, out, 24, hipMemcpyDeviceToHost, stream);
         if (e == hipSuccess) e = hipStreamSynchronize(stream);
@@ -528,8 +539,12 @@ struct sw_batch_s {
             for (const Group &g : groups)
                 HIPCHK(launch_merge(g.dim, g.model, g.variant, d_desc, g.d_tmap, g.ntiles, (uint32_t)k, stream));
             for (const Group &g : groups)
-                HIPCHK(launch_flip(g.model, g.dim, g.variant, d_desc, g.d_tmap, g.ntiles, (uint32_t)k, stream));
+                if (g.model == XY)
+                    HIPCHK(launch_flip(g.model, g.dim, g.variant, d_desc, g.d_tmap, g.ntiles, (uint32_t)k, stream));
         }
+        for (const Group &g : groups)
+            if (g.model != XY)
+                HIPCHK(launch_flip(g.model, g.dim, g.variant, d_desc, g.d_tmap, g.ntiles, FLIP_LAST, stream));
         HIPCHK(launch_advance(d_desc, (int)lats.size(), stream));
         return SW_OK;
     }
@@ -763,8 +778,12 @@ struct sw_server_s {
                 for (const Group &g : groups)
                     HIPCHK(launch_merge(g.dim, g.model, g.variant, d_desc, g.d_tmap, g.ntiles, (uint32_t)k, stream));
                 for (const Group &g : groups)
-                    HIPCHK(launch_flip(g.model, g.dim, g.variant, d_desc, g.d_tmap, g.ntiles, (uint32_t)k, stream));
+                    if (g.model == XY)
+                        HIPCHK(launch_flip(g.model, g.dim, g.variant, d_desc, g.d_tmap, g.ntiles, (uint32_t)k, stream));
             }
+            for (const Group &g : groups)
+                if (g.model != XY)
+                    HIPCHK(launch_flip(g.model, g.dim, g.variant, d_desc, g.d_tmap, g.ntiles, FLIP_LAST, stream));
             HIPCHK(hipStreamSynchronize(stream));
             for (size_t j = 0; j < active.size(); ++j) {
                 ServerJob &sj = *active[j];

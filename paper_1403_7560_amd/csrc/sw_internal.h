@@ -15,6 +15,10 @@ enum { TAG_BOND = 0, TAG_BOND_Z = 1, TAG_BOND_TIE = 2, TAG_CLUSTER = 3, TAG_GLOB
 // step (3)), so the flip needs no separate per-root array.
 constexpr uint32_t ROOT_FLAG = 0x80000000u;
 
+// k_flip's sweep argument that means "the last sweep of the launch chain"
+// (sweep0 + count - 1), used once per chain for Ising and Potts.
+constexpr uint32_t FLIP_LAST = 0xFFFFFFFFu;
+
 // Per-lattice descriptor read by every kernel (one per lattice in a batch).
 struct InstDesc {
     int32_t model, dim, L, q;
@@ -36,7 +40,8 @@ struct InstDesc {
     int64_t rec_row0;     // record row of sweep0 (-1: no recording)
     int64_t rec_cap;      // rows in rec (one extra scratch row follows)
     void *state;
-    uint32_t *label;
+    uint32_t *label;      // label words of even sweeps
+    uint32_t *label2;     // label words of odd sweeps
     uint8_t *bond;
     int32_t *face;        // per direction mu: [tile][out|in][F_mu]
     int64_t face_off[3];

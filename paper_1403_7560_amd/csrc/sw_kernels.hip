@@ -244,6 +244,20 @@ __device__ __forceinline__ uint32_t zero_bytes(uint32_t t)
     return ~(((t & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | t) & 0x80808080u;
 }
 
+// Label words of sweep n: even sweeps in `label`, odd sweeps in `label2`, so
+// that a sweep reads the previous sweep's clusters while it writes its own.
+__device__ __forceinline__ uint32_t *labels_of(const InstDesc &d, uint32_t n)
+{
+    return (n & 1u) ? d.label2 : d.label;
+}
+
+// State byte of a site whose cluster's decision is dec (Ising: bit -> +-1).
+template <int MODEL>
+__device__ __forceinline__ uint32_t state_of_decision(uint32_t dec)
+{
+    return (MODEL == ISING) ? (dec ? 0xFFu : 0x01u) : dec;
+}
+
 // Value held by lane + 1 of the wavefront (DPP wavefront shift; lane 63 gets 0).
 __device__ __forceinline__ uint32_t from_right(uint32_t v)
 {
@@ -422,7 +436,12 @@ k_bond(const InstDesc *__restrict__ descs,
     const bool bits_dec = (MODEL != POTTS) || d.q == 2;
     const uint32_t key0 = d.key0, key1 = d.key1, rep = d.rep;
     const GLOBAL S *g_st = (const GLOBAL S *)d.state;
-    GLOBAL uint32_t *g_label = (GLOBAL uint32_t *)d.label;
+    GLOBAL uint32_t *g_label = (GLOBAL uint32_t *)labels_of(d, n);
+    // Ising / Potts after the first sweep of a launch chain: the states in HBM
+    // are one sweep old; each site's state is its cluster's decision in the
+    // previous sweep's labels (step (3) of that sweep, done here)
+    const bool from_labels = (MODEL != XY) && full && k > 0;
+    GLOBAL uint32_t *lab_prev = (GLOBAL uint32_t *)labels_of(d, n - 1u);
     const uint32_t uL = (uint32_t)L;
     const uint32_t gx = (uint32_t)(x0 + c);
     const uint32_t gxr = (x0 + ex == L) ? 0u : (uint32_t)(x0 + ex);  // column right of the tile
@@ -492,15 +511,66 @@ k_bond(const InstDesc *__restrict__ descs,
             return cv;
         } else {
             vs = 0;
+            if (from_labels) {
+                uint32_t w = lab_prev[g];
+                while (!(w & ROOT_FLAG)) w = lab_prev[w];
+                return (V)state_of_decision<MODEL>(w & 0xffu);
+            }
             return (V)(uint8_t)g_st[g];
         }
     };
+    if (!IS_XY && from_labels) {
+        // per half of the rows: every row's label word, then all their tile
+        // roots' words, in flight together; chains the merge made longer walked
+        // in lock-step rounds; the tile root pointed at the final root
+        constexpr int RH = (R >= 8) ? R / 2 : R;
 #pragma unroll
-    for (int j = 0; j < R; ++j) {
-        own[j] = 0;
-        ownS[j] = 0;
-        if (vc && row_ok(j)) own[j] = value_at(gat(gx, row_y(j), row_z(j)), ownS[j]);
+        for (int h = 0; h < R; h += RH) {
+            uint32_t w[RH], cur[RH], val[RH];
+#pragma unroll
+            for (int i = 0; i < RH; ++i) {
+                w[i] = ROOT_FLAG;
+                if (vc && row_ok(h + i)) w[i] = lab_prev[gat(gx, row_y(h + i), row_z(h + i))];
+            }
+#pragma unroll
+            for (int i = 0; i < RH; ++i) {
+                cur[i] = w[i];
+                val[i] = (w[i] & ROOT_FLAG) ? w[i] : lab_prev[w[i]];
+            }
+            bool more = false;
+#pragma unroll
+            for (int i = 0; i < RH; ++i) more |= !(val[i] & ROOT_FLAG);
+            while (__any(more)) {
+                more = false;
+#pragma unroll
+                for (int i = 0; i < RH; ++i) {
+                    if (!(val[i] & ROOT_FLAG)) {
+                        cur[i] = val[i];
+                        val[i] = lab_prev[cur[i]];
+                        more |= !(val[i] & ROOT_FLAG);
+                    }
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < RH; ++i) {
+                if (!(w[i] & ROOT_FLAG) && cur[i] != w[i]) lab_prev[w[i]] = cur[i];
+                own[h + i] = (vc && row_ok(h + i)) ? (V)state_of_decision<MODEL>(val[i] & 0xffu) : (V)0;
+                ownS[h + i] = 0;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            own[j] = 0;
+            ownS[j] = 0;
+            if (vc && row_ok(j)) own[j] = value_at(gat(gx, row_y(j), row_z(j)), ownS[j]);
+        }
     }
+    // state byte of a site outside this wavefront's rows (halo, next block)
+    auto state_byte = [&](uint32_t g) -> uint32_t {
+        V unused;
+        return (uint32_t)value_at(g, unused);
+    };
     // halo column: XY: lane j < R holds the site right of the tile in row j;
     // Ising / Potts: lane g < NG holds that column's four rows of group g
     V hx = 0, hxS = 0;
@@ -514,7 +584,7 @@ k_bond(const InstDesc *__restrict__ descs,
         for (int m = 0; m < 4; ++m) {
             const int j = 4 * c + m;
             const int ly = DIM == 2 ? r0 + j : j % TY, lz = DIM == 2 ? 0 : r0 / TY + j / TY;
-            if (ly < ey && lz < ez) hxg |= (uint32_t)(uint8_t)g_st[gat(gxr, ly, lz)] << (8 * m);
+            if (ly < ey && lz < ez) hxg |= state_byte(gat(gxr, ly, lz)) << (8 * m);
         }
     }
 
@@ -567,7 +637,7 @@ k_bond(const InstDesc *__restrict__ descs,
                 uint32_t nb;
                 const bool nb_own = DIM == 2 ? (jf + 4 < R && l3 + 1 < ey) : (l3 + 1 < TY && l3 + 1 < ey);
                 if (nb_own) nb = P[gi + 1 < NG ? gi + 1 : gi] & 0xffu;
-                else nb = vc ? (uint32_t)(uint8_t)g_st[gat(gx, l3 + 1, z3)] : 0u;
+                else nb = vc ? state_byte(gat(gx, l3 + 1, z3)) : 0u;
                 PU = __builtin_amdgcn_alignbyte(nb, P[gi], 1);
             } else {
 #pragma unroll
@@ -576,7 +646,7 @@ k_bond(const InstDesc *__restrict__ descs,
                     if (!row_ok(j)) continue;
                     uint32_t ub;
                     if (row_y(j) + 1 < ey && m < 3) ub = (P[gi] >> (8 * (m + 1))) & 0xffu;
-                    else ub = vc ? (uint32_t)(uint8_t)g_st[gat(gx, row_y(j) + 1, row_z(j))] : 0u;
+                    else ub = vc ? state_byte(gat(gx, row_y(j) + 1, row_z(j))) : 0u;
                     PU |= ub << (8 * m);
                 }
             }
@@ -590,7 +660,7 @@ k_bond(const InstDesc *__restrict__ descs,
 #pragma unroll
                     for (int m = 0; m < 4; ++m)
                         if (row_ok(jf + m))
-                            PZ |= (uint32_t)(uint8_t)g_st[gat(gx, row_y(jf + m), lz + 1)] << (8 * m);
+                            PZ |= state_byte(gat(gx, row_y(jf + m), lz + 1)) << (8 * m);
                 }
             }
             // +x neighbours: lane c + 1, the last column from the halo
@@ -911,64 +981,6 @@ k_bond(const InstDesc *__restrict__ descs,
 }
 
 // ---------------------------------------------------------------------------
-// Global label equivalence across tile faces.  One workgroup per tile: for
-// every active bond across one of the tile's +mu faces, the two tile roots
-// are linked on the global label words, the larger under the smaller, with
-// device-scope atomicMin (Hawick's atomicMin on R[label], retried until it
-// links, so one pass reaches the fixed point).  A cluster crosses a face at
-// many sites with the same pair of tile roots: an LDS hash set of the pairs
-// seen lets only the first such bond make the (global, atomic) union.
-// ---------------------------------------------------------------------------
-template <int DIM>
-__global__ void __launch_bounds__(256) k_merge(const InstDesc *__restrict__ descs,
-                                               const int2 *__restrict__ tmap, uint32_t k)
-{
-    constexpr int HB = (DIM == 2) ? 256 : 2048;  // hash slots (about 2x the face elements)
-    constexpr unsigned long long EMPTY = ~0ull;
-    __shared__ unsigned long long s_set[HB];
-    const int2 tm = tmap[tile_slot()];
-    if (tm.x < 0) return;
-    const InstDesc &d = descs[tm.x];
-    if (k >= d.count) return;
-    const int t = tm.y;
-    const int tid = threadIdx.x;
-    for (int h = tid; h < HB; h += 256) s_set[h] = EMPTY;
-    __syncthreads();
-    const int tc[3] = {t % d.tiles[0], (t / d.tiles[0]) % d.tiles[1],
-                       (DIM == 3) ? t / (d.tiles[0] * d.tiles[1]) : 0};
-#pragma unroll
-    for (int mu = 0; mu < DIM; ++mu) {
-        if (d.tiles[mu] == 1) continue;
-        const int F = d.face_len[mu];
-        int cn[3] = {tc[0], tc[1], tc[2]};
-        cn[mu] = (cn[mu] + 1 == d.tiles[mu]) ? 0 : cn[mu] + 1;
-        const int nb = cn[0] + d.tiles[0] * (cn[1] + d.tiles[1] * cn[2]);
-        const GLOBAL int32_t *fo = (const GLOBAL int32_t *)d.face + d.face_off[mu] + (int64_t)t * 2 * F;
-        const GLOBAL int32_t *fi = (const GLOBAL int32_t *)d.face + d.face_off[mu] + (int64_t)nb * 2 * F + F;
-        for (int kk = tid; kk < F; kk += 256) {
-            const int32_t a = fo[kk];
-            if (a < 0) continue;
-            const int32_t b = fi[kk];
-            // the previous face element with the same pair makes this union
-            if (kk > 0 && fo[kk - 1] == a && fi[kk - 1] == b) continue;
-            const unsigned long long key = ((unsigned long long)(uint32_t)a << 32) | (uint32_t)b;
-            uint32_t h = ((uint32_t)a * 0x9E3779B1u) ^ ((uint32_t)b * 0x85EBCA77u);
-            bool fresh = true;
-            for (int probe = 0; probe < 8; ++probe) {
-                h = (h + (uint32_t)probe) & (HB - 1);
-                const unsigned long long old = atomicCAS(&s_set[h], EMPTY, key);
-                if (old == EMPTY) break;  // inserted: this thread links the pair
-                if (old == key) {
-                    fresh = false;  // seen before in this tile
-                    break;
-                }
-            }
-            if (fresh) gunion(d.label, (uint32_t)a, (uint32_t)b);
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
 // Reduction of the per-tile measurement partials into one record row, in a
 // fixed order (deterministic, also for the XY sums).  Workgroup t of a
 // lattice reduces slots t, t + ntiles, ... (XY: workgroup 0 all three).
@@ -1015,6 +1027,73 @@ __device__ void reduce_partials(const InstDesc &d, int t, int64_t row)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Global label equivalence across tile faces.  One workgroup per tile: for
+// every active bond across one of the tile's +mu faces, the two tile roots
+// are linked on the global label words, the larger under the smaller, with
+// device-scope atomicMin (Hawick's atomicMin on R[label], retried until it
+// links, so one pass reaches the fixed point).  A cluster crosses a face at
+// many sites with the same pair of tile roots: an LDS hash set of the pairs
+// seen lets only the first such bond make the (global, atomic) union.  The
+// first workgroups of a lattice also reduce the sweep's measurement partials.
+// ---------------------------------------------------------------------------
+template <int DIM>
+__global__ void __launch_bounds__(256) k_merge(const InstDesc *__restrict__ descs,
+                                               const int2 *__restrict__ tmap, uint32_t k)
+{
+    constexpr int HB = (DIM == 2) ? 256 : 2048;  // hash slots (about 2x the face elements)
+    constexpr unsigned long long EMPTY = ~0ull;
+    __shared__ unsigned long long s_set[HB];
+    const int2 tm = tmap[tile_slot()];
+    if (tm.x < 0) return;
+    const InstDesc &d = descs[tm.x];
+    if (k >= d.count) return;
+    const int t = tm.y;
+    const int tid = threadIdx.x;
+    // the first workgroups of a lattice also reduce the sweep's measurement
+    if (d.measure && d.rec_row0 >= 0 && d.rec_row0 + (int64_t)k < d.rec_cap &&
+        (t < d.nslots || (d.model == XY && t == 0))) {
+        if (d.model == ISING) reduce_partials<ISING>(d, t, d.rec_row0 + (int64_t)k);
+        else if (d.model == POTTS) reduce_partials<POTTS>(d, t, d.rec_row0 + (int64_t)k);
+        else reduce_partials<XY>(d, t, d.rec_row0 + (int64_t)k);
+    }
+    uint32_t *lab = labels_of(d, d.sweep0 + k);
+    for (int h = tid; h < HB; h += 256) s_set[h] = EMPTY;
+    __syncthreads();
+    const int tc[3] = {t % d.tiles[0], (t / d.tiles[0]) % d.tiles[1],
+                       (DIM == 3) ? t / (d.tiles[0] * d.tiles[1]) : 0};
+#pragma unroll
+    for (int mu = 0; mu < DIM; ++mu) {
+        if (d.tiles[mu] == 1) continue;
+        const int F = d.face_len[mu];
+        int cn[3] = {tc[0], tc[1], tc[2]};
+        cn[mu] = (cn[mu] + 1 == d.tiles[mu]) ? 0 : cn[mu] + 1;
+        const int nb = cn[0] + d.tiles[0] * (cn[1] + d.tiles[1] * cn[2]);
+        const GLOBAL int32_t *fo = (const GLOBAL int32_t *)d.face + d.face_off[mu] + (int64_t)t * 2 * F;
+        const GLOBAL int32_t *fi = (const GLOBAL int32_t *)d.face + d.face_off[mu] + (int64_t)nb * 2 * F + F;
+        for (int kk = tid; kk < F; kk += 256) {
+            const int32_t a = fo[kk];
+            if (a < 0) continue;
+            const int32_t b = fi[kk];
+            // the previous face element with the same pair makes this union
+            if (kk > 0 && fo[kk - 1] == a && fi[kk - 1] == b) continue;
+            const unsigned long long key = ((unsigned long long)(uint32_t)a << 32) | (uint32_t)b;
+            uint32_t h = ((uint32_t)a * 0x9E3779B1u) ^ ((uint32_t)b * 0x85EBCA77u);
+            bool fresh = true;
+            for (int probe = 0; probe < 8; ++probe) {
+                h = (h + (uint32_t)probe) & (HB - 1);
+                const unsigned long long old = atomicCAS(&s_set[h], EMPTY, key);
+                if (old == EMPTY) break;  // inserted: this thread links the pair
+                if (old == key) {
+                    fresh = false;  // seen before in this tile
+                    break;
+                }
+            }
+            if (fresh) gunion(lab, (uint32_t)a, (uint32_t)b);
+        }
+    }
+}
+
 // Measurement of the current configuration alone: reduce into the scratch row.
 template <int MODEL>
 __global__ void __launch_bounds__(256) k_reduce(const InstDesc *__restrict__ descs, const int2 *__restrict__ tmap)
@@ -1048,6 +1127,10 @@ __global__ void __launch_bounds__(256, 8) k_flip(const InstDesc *__restrict__ de
     const int2 tm = tmap[tile_slot()];
     if (tm.x < 0) return;
     const InstDesc d = descs[tm.x];
+    if (k == FLIP_LAST) {
+        if (d.count == 0) return;
+        k = d.count - 1u;  // the chain's last sweep
+    }
     if (k >= d.count) return;
     const uint32_t n = d.sweep0 + k;
     const int L = d.L;
@@ -1064,15 +1147,11 @@ __global__ void __launch_bounds__(256, 8) k_flip(const InstDesc *__restrict__ de
     const int c = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int r0 = wv * R;
     const bool vc = c < ex;
-    // the first workgroups of a lattice also reduce the sweep's measurement
-    if (d.measure && d.rec_row0 >= 0 && d.rec_row0 + (int64_t)k < d.rec_cap &&
-        (t < d.nslots || (MODEL == XY && t == 0)))
-        reduce_partials<MODEL>(d, t, d.rec_row0 + (int64_t)k);
     if (MODEL == XY) {
         if (tid == 0) s_phi = xy_phi(d, n);
         __syncthreads();
     }
-    GLOBAL uint32_t *g_label = (GLOBAL uint32_t *)d.label;
+    GLOBAL uint32_t *g_label = (GLOBAL uint32_t *)labels_of(d, n);
     auto row_ok = [&](int j) -> bool {
         const int rr = r0 + j;
         return (rr % TY) < ey && (rr / TY) < ez;
@@ -1141,11 +1220,12 @@ __global__ void __launch_bounds__(256) k_canon(const InstDesc *__restrict__ desc
     const InstDesc &d = descs[inst];
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= d.N) return;
+    const uint32_t *lab = labels_of(d, d.sweep0 - 1u);  // the last sweep
     uint32_t r = (uint32_t)i;
-    uint32_t x = d.label[r];
+    uint32_t x = lab[r];
     while (!(x & ROOT_FLAG)) {
         r = x;
-        x = d.label[r];
+        x = lab[r];
     }
     out[i] = (int32_t)r;
 }
@@ -1304,11 +1384,12 @@ __global__ void __launch_bounds__(256) k_csize(const InstDesc *__restrict__ desc
     const InstDesc &d = descs[inst];
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= d.N) return;
+    const uint32_t *lab = labels_of(d, d.sweep0 - 1u);  // the last sweep
     uint32_t r = (uint32_t)i;
-    uint32_t x = d.label[r];
+    uint32_t x = lab[r];
     while (!(x & ROOT_FLAG)) {
         r = x;
-        x = d.label[r];
+        x = lab[r];
     }
     atomicAdd(size + r, 1);
 }
