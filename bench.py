@@ -45,8 +45,11 @@ DESCRIPTION = {
 
 
 def algorithmic_bytes_per_site(model):
-    # k_bond: read the state, write the bond byte and the int32 label
-    return (4 if model == 2 else 1) + 1 + 4
+    # XY k_bond: read the angle, write the bond byte and the int32 label.
+    # Ising / Potts k_bond also applies the previous sweep's cluster
+    # decisions: it reads the previous sweep's int32 label instead of the
+    # state byte, then writes the bond byte and the int32 label.
+    return 4 + 1 + 4
 
 
 def kernel_source_hash():

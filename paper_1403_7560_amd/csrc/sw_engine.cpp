@@ -95,6 +95,7 @@ struct Lattice {
     void *state = nullptr;
     uint32_t *label = nullptr;   // label words of even sweeps
     uint32_t *label2 = nullptr;  // label words of odd sweeps
+    float *theta_w[2] = {nullptr, nullptr};  // XY: angles entering even / odd sweeps
     uint8_t *bond = nullptr;
     int32_t *face = nullptr;
     int64_t *part = nullptr;
@@ -128,12 +129,13 @@ struct Lattice {
 
     void release()
     {
-        void *ptrs[] = {state, label, label2, bond, face, part, rec, d_solo, d_tmap};
+        void *ptrs[] = {state, label, label2, theta_w[0], theta_w[1], bond, face, part, rec, d_solo, d_tmap};
         for (void *p : ptrs)
             if (p) (void)hipFree(p);
         state = nullptr;
         label = nullptr;
         label2 = nullptr;
+        theta_w[0] = theta_w[1] = nullptr;
         bond = nullptr;
         face = nullptr;
         part = nullptr;
@@ -155,7 +157,8 @@ struct Lattice {
         for (int mu = 0; mu < dim; ++mu)
             if (t[mu] > 1) face += nt * 2 * (T / ext[mu]) * 4;
         const int ns = slots_for(model, q);
-        return N * (int64_t)state_bytes(model) + 2 * N * 4 + N + face + nt * ns * 8 + 1025 * ns * 8 +
+        return N * (int64_t)state_bytes(model) * (model == XY ? 3 : 1) + 2 * N * 4 + N + face + nt * ns * 8 +
+               1025 * ns * 8 +
                (int64_t)sizeof(InstDesc) + nt * 8;
     }
 
@@ -189,6 +192,8 @@ struct Lattice {
         d.state = state;
         d.label = label;
         d.label2 = label2;
+        d.theta_w[0] = theta_w[0];
+        d.theta_w[1] = theta_w[1];
         d.bond = bond;
         d.face = face;
         for (int k = 0; k < 3; ++k) {
@@ -249,6 +254,8 @@ struct Lattice {
         if (hipMalloc(&state, (size_t)N * state_bytes(model)) != hipSuccess ||
             hipMalloc(&label, (size_t)N * 4) != hipSuccess || hipMalloc(&label2, (size_t)N * 4) != hipSuccess ||
             hipMalloc(&bond, (size_t)N) != hipSuccess ||
+            (model == XY && (hipMalloc(&theta_w[0], (size_t)N * 4) != hipSuccess ||
+                             hipMalloc(&theta_w[1], (size_t)N * 4) != hipSuccess)) ||
             hipMalloc(&face, (size_t)std::max<int64_t>(face_total, 1) * 4) != hipSuccess ||
             hipMalloc(&part, (size_t)ntiles * nslots * 8) != hipSuccess ||
             hipMalloc(&d_solo, sizeof(InstDesc)) != hipSuccess ||
@@ -292,10 +299,8 @@ struct Lattice {
                 int rc = ensure_events((size_t)(4 * m));
                 if (rc) return rc;
             }
-            // Ising / Potts: each sweep's bond kernel applies the previous
-            // sweep's cluster decisions; the chain's last decisions are applied
-            // once at the end.  XY flips every sweep (the mirror needs the old
-            // angle).
+            // each sweep's bond kernel applies the previous sweep's cluster
+            // decisions; the chain's last decisions are applied once at the end
             for (int64_t k = 0; k < m; ++k) {
                 hipEvent_t *ev = profiling ? &events[(size_t)(4 * k)] : nullptr;
                 if (ev) HIPCHK(hipEventRecord(ev[0], stream));
@@ -303,9 +308,8 @@ struct Lattice {
                 if (ev) HIPCHK(hipEventRecord(ev[1], stream));
                 HIPCHK(launch_merge(dim, model, variant, d_solo, d_tmap, ntiles, (uint32_t)k, stream));
                 if (ev && profiling > 1) HIPCHK(hipEventRecord(ev[2], stream));
-                if (model == XY) HIPCHK(launch_flip(model, dim, variant, d_solo, d_tmap, ntiles, (uint32_t)k, stream));
             }
-            if (model != XY) HIPCHK(launch_flip(model, dim, variant, d_solo, d_tmap, ntiles, FLIP_LAST, stream));
+            HIPCHK(launch_flip(model, dim, variant, d_solo, d_tmap, ntiles, FLIP_LAST, stream));
             HIPCHK(hipStreamSynchronize(stream));
             if (profiling) {
                 const int nk = profiling > 1 ? 2 : 1;
@@ -538,13 +542,9 @@ struct sw_batch_s {
                 HIPCHK(launch_bond(g.model, g.dim, g.variant, d_desc, g.d_tmap, g.ntiles, (uint32_t)k, 0, stream));
             for (const Group &g : groups)
                 HIPCHK(launch_merge(g.dim, g.model, g.variant, d_desc, g.d_tmap, g.ntiles, (uint32_t)k, stream));
-            for (const Group &g : groups)
-                if (g.model == XY)
-                    HIPCHK(launch_flip(g.model, g.dim, g.variant, d_desc, g.d_tmap, g.ntiles, (uint32_t)k, stream));
         }
         for (const Group &g : groups)
-            if (g.model != XY)
-                HIPCHK(launch_flip(g.model, g.dim, g.variant, d_desc, g.d_tmap, g.ntiles, FLIP_LAST, stream));
+            HIPCHK(launch_flip(g.model, g.dim, g.variant, d_desc, g.d_tmap, g.ntiles, FLIP_LAST, stream));
         HIPCHK(launch_advance(d_desc, (int)lats.size(), stream));
         return SW_OK;
     }
@@ -777,13 +777,9 @@ struct sw_server_s {
                     HIPCHK(launch_bond(g.model, g.dim, g.variant, d_desc, g.d_tmap, g.ntiles, (uint32_t)k, 0, stream));
                 for (const Group &g : groups)
                     HIPCHK(launch_merge(g.dim, g.model, g.variant, d_desc, g.d_tmap, g.ntiles, (uint32_t)k, stream));
-                for (const Group &g : groups)
-                    if (g.model == XY)
-                        HIPCHK(launch_flip(g.model, g.dim, g.variant, d_desc, g.d_tmap, g.ntiles, (uint32_t)k, stream));
             }
             for (const Group &g : groups)
-                if (g.model != XY)
-                    HIPCHK(launch_flip(g.model, g.dim, g.variant, d_desc, g.d_tmap, g.ntiles, FLIP_LAST, stream));
+                HIPCHK(launch_flip(g.model, g.dim, g.variant, d_desc, g.d_tmap, g.ntiles, FLIP_LAST, stream));
             HIPCHK(hipStreamSynchronize(stream));
             for (size_t j = 0; j < active.size(); ++j) {
                 ServerJob &sj = *active[j];

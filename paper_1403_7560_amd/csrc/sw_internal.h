@@ -42,6 +42,7 @@ struct InstDesc {
     void *state;
     uint32_t *label;      // label words of even sweeps
     uint32_t *label2;     // label words of odd sweeps
+    float *theta_w[2];    // XY: angles entering even / odd sweeps of a launch chain
     uint8_t *bond;
     int32_t *face;        // per direction mu: [tile][out|in][F_mu]
     int64_t face_off[3];

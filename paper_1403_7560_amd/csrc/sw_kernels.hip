@@ -16,10 +16,10 @@
 //            that crosses a tile face, link the larger root under the smaller
 //            with device-scope atomicMin (Hawick's atomicMin on R[label],
 //            retried until linked, so one pass reaches the fixed point).
-//   k_flip   every site takes its root's decision (Ising +-1, Potts state,
-//            XY mirror), following label -> tile root -> final root with the
-//            loads of all its rows in flight together.  The first workgroups
-//            also reduce the sweep's measurement.
+//   k_flip   at the end of a launch chain, every site takes its root's
+//            decision of the chain's last sweep (Ising +-1, Potts state, XY
+//            mirror); within the chain k_bond applies each sweep's decisions
+//            as it reads the next sweep's incoming states.
 //
 // Kernels read a per-lattice descriptor and a tile map, so one launch covers
 // any number of lattices of one (model, dim) group (the batched form).
@@ -318,13 +318,13 @@ __device__ __forceinline__ void xy_sincos(float th, const double2 *tab, double &
 
 // XY bond test, exact form: u = (P 2^16 + S) 2^-32 < -expm1(-(2 beta s_i) s_j)
 // with s = cos(theta - phi) in FP64, decided from the 16-bit primary alone
-// unless u's interval straddles p.  The angles are re-read from HBM: this
-// runs only when the fast test below cannot decide.
-__device__ __noinline__ uint32_t xy_bond_exact(const float *th, uint32_t gi, uint32_t gj, double phi,
-                                               double two_beta, uint32_t p, uint32_t key0, uint32_t key1,
-                                               uint32_t rep, uint32_t n, int dim, int mu)
+// unless u's interval straddles p.  Runs only when the fast test below cannot
+// decide.
+__device__ __noinline__ uint32_t xy_bond_exact(float ti, float tj, uint32_t gi, double phi, double two_beta,
+                                               uint32_t p, uint32_t key0, uint32_t key1, uint32_t rep, uint32_t n,
+                                               int dim, int mu)
 {
-    const double si = cos((double)th[gi] - phi), sj = cos((double)th[gj] - phi);
+    const double si = cos((double)ti - phi), sj = cos((double)tj - phi);
     const double x = (two_beta * si) * sj;
     const double pr = -expm1(-x);
     const double lo = (double)p * 0x1p-16, hi = (double)(p + 1u) * 0x1p-16;
@@ -410,7 +410,7 @@ k_bond(const InstDesc *__restrict__ descs,
     int *s_hist = (int *)&s_q[0][0];
     static_assert(4 * QCAP >= 256, "histogram fits the queues");
     __shared__ double s_red[4][3];
-    __shared__ double s_phi[3];  // XY: phi, cos phi, sin phi
+    __shared__ double s_phi[4];  // XY: phi, cos phi, sin phi, previous sweep's phi
     __shared__ double2 s_cs[IS_XY ? XY_TAB : 1];  // XY: cos/sin(k 2pi/128)
 
     const int2 tm = tmap[tile_slot()];
@@ -437,10 +437,11 @@ k_bond(const InstDesc *__restrict__ descs,
     const uint32_t key0 = d.key0, key1 = d.key1, rep = d.rep;
     const GLOBAL S *g_st = (const GLOBAL S *)d.state;
     GLOBAL uint32_t *g_label = (GLOBAL uint32_t *)labels_of(d, n);
-    // Ising / Potts after the first sweep of a launch chain: the states in HBM
-    // are one sweep old; each site's state is its cluster's decision in the
-    // previous sweep's labels (step (3) of that sweep, done here)
-    const bool from_labels = (MODEL != XY) && full && k > 0;
+    // After the first sweep of a launch chain the states in HBM are stale: a
+    // site's incoming state is its cluster's decision in the previous sweep's
+    // labels (step (3) of that sweep, done here) -- Ising / Potts the decision
+    // itself, XY the previous sweep's angle mirrored or kept.
+    const bool from_labels = full && k > 0;
     GLOBAL uint32_t *lab_prev = (GLOBAL uint32_t *)labels_of(d, n - 1u);
     const uint32_t uL = (uint32_t)L;
     const uint32_t gx = (uint32_t)(x0 + c);
@@ -474,6 +475,7 @@ k_bond(const InstDesc *__restrict__ descs,
         s_phi[0] = ph;
         s_phi[1] = cp;
         s_phi[2] = sp;
+        s_phi[3] = from_labels ? xy_phi(d, n - 1u) : 0.0;
     }
     if (MODEL == POTTS && meas)
         for (int q = tid; q < d.q; q += 256) s_hist[q] = 0;
@@ -498,15 +500,27 @@ k_bond(const InstDesc *__restrict__ descs,
     }
     if (IS_XY || (MODEL == POTTS && meas)) __syncthreads();
     const double phi = IS_XY ? s_phi[0] : 0.0, cphi = IS_XY ? s_phi[1] : 0.0, sphi = IS_XY ? s_phi[2] : 0.0;
+    const double phi_prev = IS_XY ? s_phi[3] : 0.0;
 
     // ---- states of the wave's rows, their +y/+z rows and the +x halo column --
     // Ising / Potts keep the states; XY keeps (cos theta, sin theta) in FP64.
     typedef typename LaneValue<MODEL>::type V;
     V own[R], ownS[R];
+    // XY: the angles entering the previous sweep of the chain, and this sweep's
+    const GLOBAL float *th_prev = IS_XY ? (const GLOBAL float *)(((n - 1u) & 1u) ? d.theta_w[1] : d.theta_w[0]) : nullptr;
+    GLOBAL float *th_cur = IS_XY ? (GLOBAL float *)((n & 1u) ? d.theta_w[1] : d.theta_w[0]) : nullptr;
+    // XY: incoming angle of site g
+    auto theta_in = [&](uint32_t g) -> float {
+        if (!from_labels) return ((const GLOBAL float *)d.state)[g];
+        uint32_t w = lab_prev[g];
+        while (!(w & ROOT_FLAG)) w = lab_prev[w];
+        const float t = th_prev[g];
+        return (w & 1u) ? xy_reflect(t, phi_prev) : t;
+    };
     auto value_at = [&](uint32_t g, V &vs) -> V {
         if constexpr (IS_XY) {
             double sv, cv;
-            xy_sincos(((const GLOBAL float *)d.state)[g], s_cs, cv, sv);
+            xy_sincos(theta_in(g), s_cs, cv, sv);
             vs = sv;
             return cv;
         } else {
@@ -519,7 +533,21 @@ k_bond(const InstDesc *__restrict__ descs,
             return (V)(uint8_t)g_st[g];
         }
     };
-    if (!IS_XY && from_labels) {
+    // the wavefront's own rows; XY stores the incoming angles for the next sweep
+    auto set_own = [&](int j, uint32_t g, uint32_t dec, float th_old) {
+        if constexpr (IS_XY) {
+            const float th = from_labels ? ((dec & 1u) ? xy_reflect(th_old, phi_prev) : th_old) : th_old;
+            if (full) th_cur[g] = th;
+            double sv, cv;
+            xy_sincos(th, s_cs, cv, sv);
+            own[j] = cv;
+            ownS[j] = sv;
+        } else {
+            own[j] = from_labels ? (V)state_of_decision<MODEL>(dec & 0xffu) : (V)(uint8_t)g_st[g];
+            ownS[j] = 0;
+        }
+    };
+    if (from_labels) {
         // per half of the rows: every row's label word, then all their tile
         // roots' words, in flight together; chains the merge made longer walked
         // in lock-step rounds; the tile root pointed at the final root
@@ -527,10 +555,16 @@ k_bond(const InstDesc *__restrict__ descs,
 #pragma unroll
         for (int h = 0; h < R; h += RH) {
             uint32_t w[RH], cur[RH], val[RH];
+            float tho[RH];
 #pragma unroll
             for (int i = 0; i < RH; ++i) {
                 w[i] = ROOT_FLAG;
-                if (vc && row_ok(h + i)) w[i] = lab_prev[gat(gx, row_y(h + i), row_z(h + i))];
+                tho[i] = 0.0f;
+                if (vc && row_ok(h + i)) {
+                    const uint32_t g = gat(gx, row_y(h + i), row_z(h + i));
+                    w[i] = lab_prev[g];
+                    if (IS_XY) tho[i] = th_prev[g];
+                }
             }
 #pragma unroll
             for (int i = 0; i < RH; ++i) {
@@ -554,8 +588,9 @@ k_bond(const InstDesc *__restrict__ descs,
 #pragma unroll
             for (int i = 0; i < RH; ++i) {
                 if (!(w[i] & ROOT_FLAG) && cur[i] != w[i]) lab_prev[w[i]] = cur[i];
-                own[h + i] = (vc && row_ok(h + i)) ? (V)state_of_decision<MODEL>(val[i] & 0xffu) : (V)0;
+                own[h + i] = 0;
                 ownS[h + i] = 0;
+                if (vc && row_ok(h + i)) set_own(h + i, gat(gx, row_y(h + i), row_z(h + i)), val[i], tho[i]);
             }
         }
     } else {
@@ -563,7 +598,10 @@ k_bond(const InstDesc *__restrict__ descs,
         for (int j = 0; j < R; ++j) {
             own[j] = 0;
             ownS[j] = 0;
-            if (vc && row_ok(j)) own[j] = value_at(gat(gx, row_y(j), row_z(j)), ownS[j]);
+            if (vc && row_ok(j)) {
+                const uint32_t g = gat(gx, row_y(j), row_z(j));
+                set_own(j, g, 0u, IS_XY ? ((const GLOBAL float *)d.state)[g] : 0.0f);
+            }
         }
     }
     // state byte of a site outside this wavefront's rows (halo, next block)
@@ -763,16 +801,16 @@ k_bond(const InstDesc *__restrict__ descs,
                     uint32_t onz = 0;
                     if (DIM == 3) onz = xy_bond_fast(d.two_beta, si, zn * cphi + znS * sphi, pz);
                     if ((onx | ony | onz) & 2u) {  // rare: p within the margin of the primary interval
-                        const float *th = (const float *)d.state;
+                        const float ti = theta_in(g);
                         if (onx == 2u)
-                            onx = xy_bond_exact(th, g, (c == ex - 1) ? gat(gxr, ly, lz) : g + 1u, phi, d.two_beta,
-                                                px, key0, key1, rep, n, DIM, 0);
+                            onx = xy_bond_exact(ti, theta_in((c == ex - 1) ? gat(gxr, ly, lz) : g + 1u), g, phi,
+                                                d.two_beta, px, key0, key1, rep, n, DIM, 0);
                         if (ony == 2u)
-                            ony = xy_bond_exact(th, g, gat(gx, ly + 1, lz), phi, d.two_beta, py, key0, key1, rep, n,
-                                                DIM, 1);
+                            ony = xy_bond_exact(ti, theta_in(gat(gx, ly + 1, lz)), g, phi, d.two_beta, py, key0,
+                                                key1, rep, n, DIM, 1);
                         if (DIM == 3 && onz == 2u)
-                            onz = xy_bond_exact(th, g, gat(gx, ly, lz + 1), phi, d.two_beta, pz, key0, key1, rep, n,
-                                                DIM, 2);
+                            onz = xy_bond_exact(ti, theta_in(gat(gx, ly, lz + 1)), g, phi, d.two_beta, pz, key0,
+                                                key1, rep, n, DIM, 2);
                     }
                     bxg[gi] |= onx << (8 * m + 7);
                     byg[gi] |= ony << (8 * m + 7);
@@ -1071,12 +1109,19 @@ __global__ void __launch_bounds__(256) k_merge(const InstDesc *__restrict__ desc
         const int nb = cn[0] + d.tiles[0] * (cn[1] + d.tiles[1] * cn[2]);
         const GLOBAL int32_t *fo = (const GLOBAL int32_t *)d.face + d.face_off[mu] + (int64_t)t * 2 * F;
         const GLOBAL int32_t *fi = (const GLOBAL int32_t *)d.face + d.face_off[mu] + (int64_t)nb * 2 * F + F;
-        for (int kk = tid; kk < F; kk += 256) {
-            const int32_t a = fo[kk];
+        for (int k0 = 0; k0 < F; k0 += 256) {
+            const int kk = k0 + tid;
+            const int32_t a = (kk < F) ? fo[kk] : -1;
+            const int32_t b = (kk < F && a >= 0) ? fi[kk] : -1;
+            // the previous face element (lane - 1; lane 0 loads it) with the
+            // same pair makes this union
+            int32_t pa = (int32_t)from_left((uint32_t)a), pb = (int32_t)from_left((uint32_t)b);
+            if ((tid & 63) == 0 && kk > 0 && kk < F) {
+                pa = fo[kk - 1];
+                pb = (pa >= 0) ? fi[kk - 1] : -1;
+            }
             if (a < 0) continue;
-            const int32_t b = fi[kk];
-            // the previous face element with the same pair makes this union
-            if (kk > 0 && fo[kk - 1] == a && fi[kk - 1] == b) continue;
+            if (kk > 0 && pa == a && pb == b) continue;
             const unsigned long long key = ((unsigned long long)(uint32_t)a << 32) | (uint32_t)b;
             uint32_t h = ((uint32_t)a * 0x9E3779B1u) ^ ((uint32_t)b * 0x85EBCA77u);
             bool fresh = true;
@@ -1106,7 +1151,8 @@ __global__ void __launch_bounds__(256) k_reduce(const InstDesc *__restrict__ des
 }
 
 // ---------------------------------------------------------------------------
-// (3) every site takes its cluster root's decision.
+// (3) every site takes its cluster root's decision -- once per launch chain,
+// for its last sweep (the bond kernel applies the earlier sweeps' decisions).
 //
 // A site's label word is its tile root's global index (or, for a root, ROOT
 // | decision); the merge may have linked tile roots to roots elsewhere.  Lane
@@ -1117,7 +1163,7 @@ __global__ void __launch_bounds__(256) k_reduce(const InstDesc *__restrict__ des
 // so that later workgroups take one hop.
 // ---------------------------------------------------------------------------
 template <int MODEL, int DIM, int TX, int TY, int TZ>
-__global__ void __launch_bounds__(256, 8) k_flip(const InstDesc *__restrict__ descs,
+__global__ void __launch_bounds__(256, (MODEL == XY) ? 4 : 8) k_flip(const InstDesc *__restrict__ descs,
                                               const int2 *__restrict__ tmap, uint32_t k)
 {
     constexpr int ROWS = TY * TZ;
@@ -1205,9 +1251,10 @@ __global__ void __launch_bounds__(256, 8) k_flip(const InstDesc *__restrict__ de
                 ((GLOBAL int8_t *)d.state)[g] = dec ? (int8_t)-1 : (int8_t)1;
             } else if (MODEL == POTTS) {
                 ((GLOBAL uint8_t *)d.state)[g] = (uint8_t)dec;
-            } else if (dec) {
-                GLOBAL float *th = (GLOBAL float *)d.state;
-                th[g] = xy_reflect(th[g], phi);
+            } else {
+                // the angle that entered the sweep, mirrored or kept
+                const float t = ((const GLOBAL float *)((n & 1u) ? d.theta_w[1] : d.theta_w[0]))[g];
+                ((GLOBAL float *)d.state)[g] = dec ? xy_reflect(t, phi) : t;
             }
         }
     }
