@@ -75,6 +75,11 @@ int validate(int model, int dim, int L, int q, double beta)
 // ---------------------------------------------------------------------------
 // One lattice and its device buffers.
 // ---------------------------------------------------------------------------
+struct Lattice;
+// Appends the tiles of lattice j of a tile map: those wholly inside the lattice
+// to `full`, those cut by its edge to `cut`.
+static void append_tiles(const Lattice &l, int j, std::vector<int2> &full, std::vector<int2> &cut);
+
 struct Lattice {
     int model = 0, dim = 2, L = 0, q = 2;
     double beta = 0.0;
@@ -85,6 +90,7 @@ struct Lattice {
     TileShape ts{0, 0, 0};
     int tiles[3] = {1, 1, 1};
     int ntiles = 0;
+    int nfull = 0;  // tiles wholly inside the lattice, listed first in d_tmap
     int nslots = 0;
     int64_t sweep = 0;      // index of the next sweep
     int64_t rec_count = 0;  // records since the last reset
@@ -265,8 +271,10 @@ struct Lattice {
         }
         rc = grow_records(1024);
         if (rc) return rc;
-        std::vector<int2> tm(ntiles);
-        for (int t = 0; t < ntiles; ++t) tm[t] = make_int2(0, t);
+        std::vector<int2> tm, cut;
+        append_tiles(*this, 0, tm, cut);
+        nfull = (int)tm.size();
+        tm.insert(tm.end(), cut.begin(), cut.end());
         HIPCHK(hipMemcpy(d_tmap, tm.data(), tm.size() * sizeof(int2), hipMemcpyHostToDevice));
         HIPCHK(hipMemsetAsync(bond, 0, (size_t)N, stream));
         // face slots outside the lattice (ragged tiles) are never written and
@@ -304,7 +312,7 @@ struct Lattice {
             for (int64_t k = 0; k < m; ++k) {
                 hipEvent_t *ev = profiling ? &events[(size_t)(4 * k)] : nullptr;
                 if (ev) HIPCHK(hipEventRecord(ev[0], stream));
-                HIPCHK(launch_bond(model, dim, variant, d_solo, d_tmap, ntiles, (uint32_t)k, 0, stream));
+                HIPCHK(launch_bond(model, dim, variant, d_solo, d_tmap, ntiles, nfull, (uint32_t)k, 0, stream));
                 if (ev) HIPCHK(hipEventRecord(ev[1], stream));
                 HIPCHK(launch_merge(dim, model, variant, d_solo, d_tmap, ntiles, (uint32_t)k, stream));
                 if (ev && profiling > 1) HIPCHK(hipEventRecord(ev[2], stream));
@@ -337,7 +345,7 @@ struct Lattice {
         d.count = 1;
         HIPCHK(hipMemcpyAsync(d_solo, &d, sizeof(d), hipMemcpyHostToDevice, stream));
         HIPCHK(hipStreamSynchronize(stream));
-        HIPCHK(launch_bond(model, dim, variant, d_solo, d_tmap, ntiles, 0, 1, stream));
+        HIPCHK(launch_bond(model, dim, variant, d_solo, d_tmap, ntiles, nfull, 0, 1, stream));
         HIPCHK(launch_reduce(model, d_solo, d_tmap, ntiles, stream));
         row.assign(nslots, 0);
         HIPCHK(hipMemcpyAsync(row.data(), rec + rec_cap * nslots, (size_t)nslots * 8, hipMemcpyDeviceToHost,
@@ -444,6 +452,11 @@ struct Lattice {
     }
 };
 
+static void append_tiles(const Lattice &l, int j, std::vector<int2> &full, std::vector<int2> &cut)
+{
+    for (int t = 0; t < l.ntiles; ++t) (tile_interior(l.dim, l.L, l.ts, t) ? full : cut).push_back(make_int2(j, t));
+}
+
 struct sw_ctx {
     Lattice *lat = nullptr;
     bool owned = false;
@@ -481,6 +494,7 @@ struct Group {
     int model, dim, variant;
     std::vector<int> members;
     int ntiles = 0;
+    int nfull = 0;  // leading tile-map entries wholly inside their lattice
     int2 *d_tmap = nullptr;
 };
 
@@ -515,15 +529,16 @@ struct sw_batch_s {
             auto it = index.find(key);
             if (it == index.end()) {
                 index[key] = (int)groups.size();
-                groups.push_back(Group{l.model, l.dim, l.variant, {}, 0, nullptr});
+                groups.push_back(Group{l.model, l.dim, l.variant, {}, 0, 0, nullptr});
                 it = index.find(key);
             }
             groups[it->second].members.push_back(j);
         }
         for (Group &g : groups) {
-            std::vector<int2> tm;
-            for (int j : g.members)
-                for (int t = 0; t < lats[j]->ntiles; ++t) tm.push_back(make_int2(j, t));
+            std::vector<int2> tm, cut;
+            for (int j : g.members) append_tiles(*lats[j], j, tm, cut);
+            g.nfull = (int)tm.size();
+            tm.insert(tm.end(), cut.begin(), cut.end());
             g.ntiles = (int)tm.size();
             if (hipMalloc(&g.d_tmap, tm.size() * sizeof(int2)) != hipSuccess)
                 return fail(SW_E_NOMEM, "tile map allocation failed");
@@ -539,7 +554,7 @@ struct sw_batch_s {
     {
         for (int k = 0; k < S; ++k) {
             for (const Group &g : groups)
-                HIPCHK(launch_bond(g.model, g.dim, g.variant, d_desc, g.d_tmap, g.ntiles, (uint32_t)k, 0, stream));
+                HIPCHK(launch_bond(g.model, g.dim, g.variant, d_desc, g.d_tmap, g.ntiles, g.nfull, (uint32_t)k, 0, stream));
             for (const Group &g : groups)
                 HIPCHK(launch_merge(g.dim, g.model, g.variant, d_desc, g.d_tmap, g.ntiles, (uint32_t)k, stream));
         }
@@ -671,14 +686,15 @@ struct sw_server_s {
             auto key = std::make_tuple(l.model, l.dim, l.variant);
             if (!index.count(key)) {
                 index[key] = (int)groups.size();
-                groups.push_back(Group{l.model, l.dim, l.variant, {}, 0, nullptr});
+                groups.push_back(Group{l.model, l.dim, l.variant, {}, 0, 0, nullptr});
             }
             groups[index[key]].members.push_back(j);
         }
         for (Group &g : groups) {
-            std::vector<int2> tm;
-            for (int j : g.members)
-                for (int t = 0; t < active[j]->lat->ntiles; ++t) tm.push_back(make_int2(j, t));
+            std::vector<int2> tm, cut;
+            for (int j : g.members) append_tiles(*active[j]->lat, j, tm, cut);
+            g.nfull = (int)tm.size();
+            tm.insert(tm.end(), cut.begin(), cut.end());
             g.ntiles = (int)tm.size();
             if (hipMalloc(&g.d_tmap, tm.size() * sizeof(int2)) != hipSuccess)
                 return fail(SW_E_NOMEM, "tile map allocation failed");
@@ -774,7 +790,7 @@ struct sw_server_s {
             HIPCHK(hipMemcpyAsync(d_desc, h_desc, active.size() * sizeof(InstDesc), hipMemcpyHostToDevice, stream));
             for (int64_t k = 0; k < maxc; ++k) {
                 for (const Group &g : groups)
-                    HIPCHK(launch_bond(g.model, g.dim, g.variant, d_desc, g.d_tmap, g.ntiles, (uint32_t)k, 0, stream));
+                    HIPCHK(launch_bond(g.model, g.dim, g.variant, d_desc, g.d_tmap, g.ntiles, g.nfull, (uint32_t)k, 0, stream));
                 for (const Group &g : groups)
                     HIPCHK(launch_merge(g.dim, g.model, g.variant, d_desc, g.d_tmap, g.ntiles, (uint32_t)k, stream));
             }

@@ -61,10 +61,14 @@ struct TileShape {
 int num_tile_variants(int model, int dim);
 TileShape tile_shape(int model, int dim, int variant);
 int slots_for(int model, int q);
+// Tile t of an L^dim lattice cut into tiles of shape ts lies wholly inside it.
+bool tile_interior(int dim, int L, const TileShape &ts, int t);
 
 hipError_t launch_init(const InstDesc *d_desc, int inst, const InstDesc &h, hipStream_t s);
+// The first `nfull` entries of the tile map are tiles wholly inside their
+// lattice (see append_tiles); they run the bond kernel without edge tests.
 hipError_t launch_bond(int model, int dim, int variant, const InstDesc *d_desc,
-                       const int2 *d_tmap, int ntiles, uint32_t k, int mode, hipStream_t s);
+                       const int2 *d_tmap, int ntiles, int nfull, uint32_t k, int mode, hipStream_t s);
 hipError_t launch_merge(int dim, int model, int variant, const InstDesc *d_desc, const int2 *d_tmap,
                         int ntiles, uint32_t k, hipStream_t s);
 hipError_t launch_reduce(int model, const InstDesc *d_desc, const int2 *d_tmap, int ntiles, hipStream_t s);

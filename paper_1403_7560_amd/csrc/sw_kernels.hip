@@ -382,7 +382,7 @@ template <int MODEL, int T> struct BondOccupancy {
     static constexpr int value = (MODEL == XY) ? 4 : ((T <= 4096) ? 8 : 3);
 };
 
-template <int MODEL, int DIM, int TX, int TY, int TZ>
+template <int MODEL, int DIM, int TX, int TY, int TZ, bool FULL>
 __global__ void __launch_bounds__(256, (BondOccupancy<MODEL, TX * TY * TZ>::value))
 k_bond(const InstDesc *__restrict__ descs,
                                               const int2 *__restrict__ tmap, uint32_t k, int mode)
@@ -424,13 +424,19 @@ k_bond(const InstDesc *__restrict__ descs,
     const int ty = (t / d.tiles[0]) % d.tiles[1];
     const int tz = (DIM == 3) ? t / (d.tiles[0] * d.tiles[1]) : 0;
     const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
-    const int ex = min(TX, L - x0), ey = min(TY, L - y0), ez = (DIM == 3) ? min(TZ, L - z0) : 1;
     const int tid = threadIdx.x;
     // the wavefront index is uniform: readfirstlane lets everything derived
     // from it (rows, global addresses) live in scalar registers
     const int c = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int r0 = wv * R;
-    const bool vc = c < ex;
+    // FULL: the tile lies wholly inside the lattice (every tile when the side
+    // is a multiple of the tile's); its extents are constants and no row or
+    // column needs a range test.  The host lists such tiles apart.
+    if (FULL && !((x0 + TX <= L) && (y0 + TY <= L) && (DIM == 2 || z0 + TZ <= L))) return;
+    const int ex = FULL ? TX : min(TX, L - x0);
+    const int ey = FULL ? TY : min(TY, L - y0);
+    const int ez = (DIM == 3) ? (FULL ? TZ : min(TZ, L - z0)) : 1;
+    const bool vc = FULL || c < ex;
     const bool full = (mode == 0);
     const bool meas = (mode == 1) || d.measure;
     const bool bits_dec = (MODEL != POTTS) || d.q == 2;
@@ -451,13 +457,17 @@ k_bond(const InstDesc *__restrict__ descs,
     // the plane; 3D: whole planes)
     auto row_y = [&](int j) -> int { return DIM == 2 ? r0 + j : j % TY; };
     auto row_z = [&](int j) -> int { return DIM == 2 ? 0 : r0 / TY + j / TY; };
-    auto row_ok = [&](int j) -> bool { return row_y(j) < ey && row_z(j) < ez; };
+    auto row_ok = [&](int j) -> bool { return FULL || (row_y(j) < ey && row_z(j) < ez); };
     // global index of (x, y0 + ly, z0 + lz), ly <= ey and lz <= ez wrapping
     auto gat = [&](uint32_t x, int ly, int lz) -> uint32_t {
         uint32_t y = (uint32_t)(y0 + ly), z = (uint32_t)(z0 + lz);
         if (y >= uL) y -= uL;
         if (DIM == 3 && z >= uL) z -= uL;
         return x + uL * (y + uL * z);
+    };
+    // the same for a site of the tile (ly < ey, lz < ez): nothing wraps
+    auto gin = [&](uint32_t x, int ly, int lz) -> uint32_t {
+        return x + uL * ((uint32_t)(y0 + ly) + uL * (uint32_t)(z0 + lz));
     };
     auto gidx = [&](int l) -> uint32_t {  // tile-local index -> global index
         return s_rowg[l >> 6] + (uint32_t)(l & 63);
@@ -487,7 +497,7 @@ k_bond(const InstDesc *__restrict__ descs,
         const int r = tid >> 1, half = tid & 1;
         const int ly = r % TY, lz = r / TY;
         if (ly < ey && lz < ez) {
-            const uint32_t gr = gat((uint32_t)x0, ly, lz);
+            const uint32_t gr = gin((uint32_t)x0, ly, lz);
             const uint32_t blk = (gr >> 7) + (uint32_t)half;
             const uint4 w = philox(make_uint4(blk, n, (uint32_t)TAG_CLUSTER, rep), key0, key1);
             const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
@@ -561,7 +571,7 @@ k_bond(const InstDesc *__restrict__ descs,
                 w[i] = ROOT_FLAG;
                 tho[i] = 0.0f;
                 if (vc && row_ok(h + i)) {
-                    const uint32_t g = gat(gx, row_y(h + i), row_z(h + i));
+                    const uint32_t g = gin(gx, row_y(h + i), row_z(h + i));
                     w[i] = lab_prev[g];
                     if (IS_XY) tho[i] = th_prev[g];
                 }
@@ -590,7 +600,7 @@ k_bond(const InstDesc *__restrict__ descs,
                 if (!(w[i] & ROOT_FLAG) && cur[i] != w[i]) lab_prev[w[i]] = cur[i];
                 own[h + i] = 0;
                 ownS[h + i] = 0;
-                if (vc && row_ok(h + i)) set_own(h + i, gat(gx, row_y(h + i), row_z(h + i)), val[i], tho[i]);
+                if (vc && row_ok(h + i)) set_own(h + i, gin(gx, row_y(h + i), row_z(h + i)), val[i], tho[i]);
             }
         }
     } else {
@@ -599,7 +609,7 @@ k_bond(const InstDesc *__restrict__ descs,
             own[j] = 0;
             ownS[j] = 0;
             if (vc && row_ok(j)) {
-                const uint32_t g = gat(gx, row_y(j), row_z(j));
+                const uint32_t g = gin(gx, row_y(j), row_z(j));
                 set_own(j, g, 0u, IS_XY ? ((const GLOBAL float *)d.state)[g] : 0.0f);
             }
         }
@@ -615,14 +625,14 @@ k_bond(const InstDesc *__restrict__ descs,
     uint32_t hxg = 0;
     if (IS_XY && c < R) {
         const int ly = DIM == 2 ? r0 + c : c % TY, lz = DIM == 2 ? 0 : r0 / TY + c / TY;
-        if (ly < ey && lz < ez) hx = value_at(gat(gxr, ly, lz), hxS);
+        if (ly < ey && lz < ez) hx = value_at(gin(gxr, ly, lz), hxS);
     }
     if (!IS_XY && c < NG) {
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
             const int j = 4 * c + m;
             const int ly = DIM == 2 ? r0 + j : j % TY, lz = DIM == 2 ? 0 : r0 / TY + j / TY;
-            if (ly < ey && lz < ez) hxg |= state_byte(gat(gxr, ly, lz)) << (8 * m);
+            if (ly < ey && lz < ez) hxg |= state_byte(gin(gxr, ly, lz)) << (8 * m);
         }
     }
 
@@ -744,7 +754,7 @@ k_bond(const InstDesc *__restrict__ descs,
 #pragma unroll
                     for (int m = 0; m < 4; ++m) {
                         const uint32_t bit = 0x80u << (8 * m);
-                        const uint32_t g = gat(gx, row_y(jf + m), row_z(jf + m));
+                        const uint32_t g = gin(gx, row_y(jf + m), row_z(jf + m));
                         if ((EQX & bit) && tx[m] == 0u && bond_secondary(key0, key1, rep, n, DIM, g, 0) < d.thr_lo)
                             bxg[gi] |= bit;
                         if ((EQY & bit) && ty_[m] == 0u && bond_secondary(key0, key1, rep, n, DIM, g, 1) < d.thr_lo)
@@ -785,7 +795,7 @@ k_bond(const InstDesc *__restrict__ descs,
                     rt = readlane_d(hx, j);
                     rtS = readlane_d(hxS, j);
                 }
-                const uint32_t g = gat(gx, ly, lz);
+                const uint32_t g = gin(gx, ly, lz);
                 if (meas && vc) {
                     sx_acc += own[j];
                     sy_acc += ownS[j];
@@ -803,7 +813,7 @@ k_bond(const InstDesc *__restrict__ descs,
                     if ((onx | ony | onz) & 2u) {  // rare: p within the margin of the primary interval
                         const float ti = theta_in(g);
                         if (onx == 2u)
-                            onx = xy_bond_exact(ti, theta_in((c == ex - 1) ? gat(gxr, ly, lz) : g + 1u), g, phi,
+                            onx = xy_bond_exact(ti, theta_in((c == ex - 1) ? gin(gxr, ly, lz) : g + 1u), g, phi,
                                                 d.two_beta, px, key0, key1, rep, n, DIM, 0);
                         if (ony == 2u)
                             ony = xy_bond_exact(ti, theta_in(gat(gx, ly + 1, lz)), g, phi, d.two_beta, py, key0,
@@ -824,7 +834,7 @@ k_bond(const InstDesc *__restrict__ descs,
 #pragma unroll
             for (int m = 0; m < 4; ++m)
                 if (row_ok(jf + m))
-                    ((GLOBAL uint8_t *)d.bond)[gat(gx, row_y(jf + m), row_z(jf + m))] = (uint8_t)(B >> (8 * m));
+                    ((GLOBAL uint8_t *)d.bond)[gin(gx, row_y(jf + m), row_z(jf + m))] = (uint8_t)(B >> (8 * m));
         }
     }
     auto bit_of = [&](const uint32_t *arr, int j) -> uint32_t { return (arr[j >> 2] >> (8 * (j & 3) + 7)) & 1u; };
@@ -983,8 +993,8 @@ k_bond(const InstDesc *__restrict__ descs,
             for (int m = 0; m < 4; ++m) {
                 const int j = jf + m, rr = r0 + j;
                 if (!isr[m]) continue;
-                const uint32_t g = gat(gx, row_y(j), row_z(j));
-                const uint32_t base = gat((uint32_t)x0, row_y(j), row_z(j)) >> 5;
+                const uint32_t g = gin(gx, row_y(j), row_z(j));
+                const uint32_t base = gin((uint32_t)x0, row_y(j), row_z(j)) >> 5;
                 dec[m] = (s_cw[3 * rr + (int)((g >> 5) - base)] >> (g & 31u)) & 1u;
             }
         } else if (__ballot(isr[0] || isr[1] || isr[2] || isr[3])) {
@@ -1000,7 +1010,7 @@ k_bond(const InstDesc *__restrict__ descs,
             if (!row_ok(j)) continue;
             const int ly = row_y(j), lz = row_z(j);
             const int32_t rg = (int32_t)gidx(root[j] < 0 ? 0 : root[j]);
-            if (vc) g_label[gat(gx, ly, lz)] = isr[m] ? (ROOT_FLAG | dec[m]) : (uint32_t)rg;
+            if (vc) g_label[gin(gx, ly, lz)] = isr[m] ? (ROOT_FLAG | dec[m]) : (uint32_t)rg;
             // faces for the global merge: the out side marks a bond across the face
             if (fx) {
                 if (c == ex - 1) fo0[rr] = bit_of(bxg, j) ? rg : -1;
@@ -1312,6 +1322,13 @@ TileShape tile_shape(int model, int dim, int v)
     return TileShape{0, 0, 0};
 }
 
+bool tile_interior(int dim, int L, const TileShape &ts, int t)
+{
+    const int nx = (L + ts.tx - 1) / ts.tx, ny = (L + ts.ty - 1) / ts.ty;
+    const int tx = t % nx, ty = (t / nx) % ny, tz = t / (nx * ny);
+    return (tx + 1) * ts.tx <= L && (ty + 1) * ts.ty <= L && (dim == 2 || (tz + 1) * ts.tz <= L);
+}
+
 int slots_for(int model, int q) { return model == ISING ? 2 : (model == POTTS ? 1 + q : 3); }
 
 hipError_t launch_init(const InstDesc *d_desc, int inst, const InstDesc &h, hipStream_t s)
@@ -1325,13 +1342,17 @@ hipError_t launch_init(const InstDesc *d_desc, int inst, const InstDesc &h, hipS
 }
 
 template <int MODEL, int DIM>
-static hipError_t bond_dispatch(int v, const InstDesc *dd, const int2 *tm, int nt, uint32_t k, int mode,
+static hipError_t bond_dispatch(int v, const InstDesc *dd, const int2 *tm, int nt, int nf, uint32_t k, int mode,
                                 hipStream_t s)
 {
-#define X(i, a, b, c)                                                                                 \
-    if (v == i) {                                                                                     \
-        hipLaunchKernelGGL((k_bond<MODEL, DIM, a, b, c>), dim3(nt), dim3(256), 0, s, dd, tm, k, mode); \
-        return hipGetLastError();                                                                     \
+#define X(i, a, b, c)                                                                                          \
+    if (v == i) {                                                                                              \
+        if (nf > 0)                                                                                            \
+            hipLaunchKernelGGL((k_bond<MODEL, DIM, a, b, c, true>), dim3(nf), dim3(256), 0, s, dd, tm, k, mode); \
+        if (nt > nf)                                                                                           \
+            hipLaunchKernelGGL((k_bond<MODEL, DIM, a, b, c, false>), dim3(nt - nf), dim3(256), 0, s, dd, tm + nf, \
+                               k, mode);                                                                       \
+        return hipGetLastError();                                                                              \
     }
     if constexpr (MODEL != XY && DIM == 2) { SW_VARIANTS_ISING2 }
     if constexpr (MODEL != XY && DIM == 3) { SW_VARIANTS_ISING3 }
@@ -1357,15 +1378,16 @@ static hipError_t flip_dispatch(int v, const InstDesc *dd, const int2 *tm, int n
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_bond(int model, int dim, int v, const InstDesc *dd, const int2 *tm, int nt, uint32_t k,
+hipError_t launch_bond(int model, int dim, int v, const InstDesc *dd, const int2 *tm, int nt, int nf, uint32_t k,
                        int mode, hipStream_t s)
 {
     if (nt <= 0) return hipSuccess;
-    if (model == ISING) return dim == 2 ? bond_dispatch<ISING, 2>(v, dd, tm, nt, k, mode, s)
-                                        : bond_dispatch<ISING, 3>(v, dd, tm, nt, k, mode, s);
-    if (model == POTTS) return dim == 2 ? bond_dispatch<POTTS, 2>(v, dd, tm, nt, k, mode, s)
-                                        : bond_dispatch<POTTS, 3>(v, dd, tm, nt, k, mode, s);
-    return dim == 2 ? bond_dispatch<XY, 2>(v, dd, tm, nt, k, mode, s) : bond_dispatch<XY, 3>(v, dd, tm, nt, k, mode, s);
+    if (nf < 0 || nf > nt) return hipErrorInvalidValue;
+    if (model == ISING) return dim == 2 ? bond_dispatch<ISING, 2>(v, dd, tm, nt, nf, k, mode, s)
+                                        : bond_dispatch<ISING, 3>(v, dd, tm, nt, nf, k, mode, s);
+    if (model == POTTS) return dim == 2 ? bond_dispatch<POTTS, 2>(v, dd, tm, nt, nf, k, mode, s)
+                                        : bond_dispatch<POTTS, 3>(v, dd, tm, nt, nf, k, mode, s);
+    return dim == 2 ? bond_dispatch<XY, 2>(v, dd, tm, nt, nf, k, mode, s) : bond_dispatch<XY, 3>(v, dd, tm, nt, nf, k, mode, s);
 }
 
 hipError_t launch_merge(int dim, int model, int v, const InstDesc *dd, const int2 *tm, int nt, uint32_t k,
