@@ -364,7 +364,7 @@ __device__ __forceinline__ uint32_t xy_bond_fast(double two_beta, double si, dou
 // Philox call per lane gives the words of four consecutive rows.
 //
 // Labelling scans the rows in order: the x bonds of a row form runs (ballot
-// and bit tricks); a run takes the label of its leftmost site bonded to the
+// and bit tricks); a run takes the smallest label among its sites bonded to the
 // row above (3D: or the plane behind), otherwise its own start.  Only run
 // starts are union-find nodes: s_par[start] links to the inherited label.  A
 // bonded neighbour whose label differs is an equivalence, queued and resolved
@@ -875,14 +875,18 @@ k_bond(const InstDesc *__restrict__ descs,
 
     // ---- (2) local labelling ---------------------------------------------------
     const unsigned long long upto = (c == 63) ? ~0ull : ((2ull << c) - 1ull);
-    const unsigned long long from = ~((1ull << c) - 1ull);
     int qn = 0;  // entries in this wave's queue (uniform)
     auto flush = [&]() {
         if (qn) flush_queue((lds_int *)s_par, (const lds_u32 *)s_q[wv], qn, c);
         qn = 0;
     };
+    // a ballot of one comparison is that comparison's lane mask (a compound
+    // condition is rebuilt lane by lane first)
+    auto ballot = [](bool p) -> unsigned long long { return __builtin_amdgcn_ballot_w64(p); };
+    const unsigned long long vmask = (ex >= 64) ? ~0ull : ((1ull << ex) - 1ull);  // lanes c < ex
+    // queue (a, b) from the lanes where `want` holds
     auto push = [&](bool want, int a, int b) {
-        const unsigned long long m = __ballot(want);
+        const unsigned long long m = ballot(want);
         if (!m) return;
         if (qn > QCAP - 64) flush();
         if (want) {
@@ -902,31 +906,37 @@ k_bond(const InstDesc *__restrict__ descs,
                 continue;
             }
             const int rr = r0 + j;
-            const unsigned long long xb = __ballot(vc && bit_of(bxg, j) && c + 1 < ex);
+            // x bonds to lane c + 1 < ex
+            const unsigned long long xb = ballot(bit_of(bxg, j) != 0u) & (vmask >> 1);
             if (c == 0) s_xm[rr] = xb;
             const int rs = 63 - __clzll((long long)(~(xb << 1) & upto));
-            const int re = __ffsll((long long)(~xb & from)) - 1;
-            int ca = NONE, cb = NONE;
-            if (j > 0 && row_y(j) > 0 && bit_of(byg, j > 0 ? j - 1 : 0)) ca = prevlab;
-            if (DIM == 3 && j >= TY && bit_of(bzg, j >= TY ? j - TY : 0)) cb = labr[j >= TY ? j - TY : 0];
-            if (!vc) ca = cb = NONE;
-            const int cand = min(ca, cb);
-            const unsigned long long conn = __ballot(cand != NONE);
-            const unsigned long long mr = conn >> rs;
-            const int f = mr ? rs + __ffsll((long long)mr) - 1 : 64;
-            const int fl = __builtin_amdgcn_ds_bpermute((f & 63) << 2, cand);
             const int node = rs + TX * rr;
-            const int lab = (f <= re) ? fl : node;
-            if (vc && c == rs) s_par[node] = lab;
+            // bonded to the row above / the plane behind (inside the wavefront's rows)
+            const bool up_in = j > 0 && row_y(j) > 0, back_in = DIM == 3 && j >= TY;
+            const bool ya = up_in && vc && bit_of(byg, j > 0 ? j - 1 : 0);
+            const bool zb = back_in && vc && bit_of(bzg, j >= TY ? j - TY : 0);
+            const int ca = ya ? prevlab : NONE;
+            const int cb = zb ? labr[j >= TY ? j - TY : 0] : NONE;
+            const int cand = min(ca, cb);
+            // the run's label: the smallest label its sites inherit, else its own
+            // start (every inherited label is a smaller node, so s_par stays a
+            // forest pointing downwards).  The run start seeds the slot, the
+            // bonded sites lower it, all read it back: the wavefront's LDS
+            // operations complete in order.
+            if (vc && c == rs) s_par[node] = node;
+            if (ya || zb)
+                __hip_atomic_fetch_min((lds_int *)&s_par[node], cand, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            const int lab = vc ? __hip_atomic_load((lds_int *)&s_par[node], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)
+                               : NONE;
             // a bonded neighbour with another label: one entry per stretch of equal labels
             const int cal = (int)from_left((uint32_t)ca);
-            push(ca != NONE && ca != lab && (c == rs || cal != ca), ca, lab);
+            push(ya && ca != lab && (c == rs || cal != ca), ca, lab);
             if (DIM == 3) {
                 const int cbl = (int)from_left((uint32_t)cb);
-                push(cb != NONE && cb != lab && (c == rs || cbl != cb), cb, lab);
+                push(zb && cb != lab && (c == rs || cbl != cb), cb, lab);
             }
             // periodic x bond of a tile that spans the lattice: to (0, row)
-            if (d.tiles[0] == 1) push(vc && c == ex - 1 && bit_of(bxg, j), TX * rr, lab);
+            if (d.tiles[0] == 1) push(c == ex - 1 && bit_of(bxg, j), TX * rr, lab);
             prevlab = lab;
             labr[j] = lab;
         }
