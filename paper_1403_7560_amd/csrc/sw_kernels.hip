@@ -403,7 +403,7 @@ k_bond(const InstDesc *__restrict__ descs,
     __shared__ int s_par[T];
     __shared__ unsigned long long s_xm[ROWS];  // in-tile x-bond mask of every row
     __shared__ uint32_t s_rowg[ROWS];          // global index of every row's first site
-    __shared__ uint32_t s_cw[ROWS * 3];        // cluster decision words, 3 per tile row
+    __shared__ unsigned long long s_dm[ROWS];  // cluster decision bit of every site, one word per row
     __shared__ uint32_t s_q[4][QCAP];
     // Potts histogram of the measurement: it is done before the scan fills the
     // equivalence queues, so it shares their memory
@@ -490,22 +490,25 @@ k_bond(const InstDesc *__restrict__ descs,
     if (MODEL == POTTS && meas)
         for (int q = tid; q < d.q; q += 256) s_hist[q] = 0;
     for (int r = tid; r < ROWS; r += 256) s_rowg[r] = gat((uint32_t)x0, r % TY, r / TY);
-    // Cluster decision words of every tile row (one bit per possible root):
-    // the sites g_r .. g_r + 63 of row r use words g_r/32 .. g_r/32 + 2,
-    // which lie in Philox blocks g_r/128 and g_r/128 + 1 of the cluster stream.
-    if (full && bits_dec && tid < 2 * ROWS) {
-        const int r = tid >> 1, half = tid & 1;
-        const int ly = r % TY, lz = r / TY;
+    // Cluster decision bits of every tile row (one bit per possible root): bit
+    // c of s_dm[r] is bit g mod 32 of word g/32 of the cluster stream, g the
+    // global index of site (x0 + c, row r).  The row's 64 bits lie in three
+    // consecutive words, in Philox block g_r/128 and possibly the next one.
+    if (full && bits_dec && tid < ROWS) {
+        const int r = tid, ly = r % TY, lz = r / TY;
         if (ly < ey && lz < ez) {
             const uint32_t gr = gin((uint32_t)x0, ly, lz);
-            const uint32_t blk = (gr >> 7) + (uint32_t)half;
-            const uint4 w = philox(make_uint4(blk, n, (uint32_t)TAG_CLUSTER, rep), key0, key1);
-            const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const uint32_t kk = 4 * blk + (uint32_t)i - (gr >> 5);
-                if (kk < 3u) s_cw[3 * r + (int)kk] = ws[i];
-            }
+            const uint32_t blk = gr >> 7, wo = (gr >> 5) & 3u;
+            const uint4 w0 = philox(make_uint4(blk, n, (uint32_t)TAG_CLUSTER, rep), key0, key1);
+            uint4 w1 = make_uint4(0u, 0u, 0u, 0u);
+            if (wo >= 2u) w1 = philox(make_uint4(blk + 1u, n, (uint32_t)TAG_CLUSTER, rep), key0, key1);
+            // words wo, wo + 1, wo + 2 of the sequence w0, w1
+            const uint32_t a = wo == 0u ? w0.x : wo == 1u ? w0.y : wo == 2u ? w0.z : w0.w;
+            const uint32_t b = wo == 0u ? w0.y : wo == 1u ? w0.z : wo == 2u ? w0.w : w1.x;
+            const uint32_t e = wo == 0u ? w0.z : wo == 1u ? w0.w : wo == 2u ? w1.x : w1.y;
+            const uint32_t sh = gr & 31u;
+            const uint32_t lo = __builtin_amdgcn_alignbit(b, a, sh), hi = __builtin_amdgcn_alignbit(e, b, sh);
+            s_dm[r] = ((unsigned long long)hi << 32) | lo;
         }
     }
     if (IS_XY || (MODEL == POTTS && meas)) __syncthreads();
@@ -571,15 +574,18 @@ k_bond(const InstDesc *__restrict__ descs,
                 w[i] = ROOT_FLAG;
                 tho[i] = 0.0f;
                 if (vc && row_ok(h + i)) {
-                    const uint32_t g = gin(gx, row_y(h + i), row_z(h + i));
-                    w[i] = lab_prev[g];
-                    if (IS_XY) tho[i] = th_prev[g];
+                    const uint32_t g0 = gin((uint32_t)x0, row_y(h + i), row_z(h + i));
+                    w[i] = (lab_prev + g0)[c];
+                    if (IS_XY) tho[i] = (th_prev + g0)[c];
                 }
             }
 #pragma unroll
             for (int i = 0; i < RH; ++i) {
                 cur[i] = w[i];
-                val[i] = (w[i] & ROOT_FLAG) ? w[i] : lab_prev[w[i]];
+                // a root word loads the lattice's first word instead (no branch
+                // around the load; the value is dropped)
+                const uint32_t ld = lab_prev[(w[i] & ROOT_FLAG) ? 0u : w[i]];
+                val[i] = (w[i] & ROOT_FLAG) ? w[i] : ld;
             }
             bool more = false;
 #pragma unroll
@@ -964,21 +970,25 @@ k_bond(const InstDesc *__restrict__ descs,
     __syncthreads();
     // root of every row's label: pointer jumping on all rows at once (the
     // parents only ever point to smaller nodes, so this ends)
-    int root[R];
+    // (two jumps per pass, alternating between two arrays: no copies)
+    int root[R], nxt[R];
 #pragma unroll
     for (int j = 0; j < R; ++j) root[j] = (vc && row_ok(j)) ? labr[j] : -1;
-    bool moving = true;
-    while (__any(moving)) {
+    while (true) {
+        bool moving = false;
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            nxt[j] = (FULL || root[j] >= 0) ? s_par[FULL ? root[j] : max(root[j], 0)] : -1;
+            moving |= nxt[j] != root[j];
+        }
+        if (!__any(moving)) break;  // root[] final
         moving = false;
 #pragma unroll
         for (int j = 0; j < R; ++j) {
-            if (root[j] < 0) continue;
-            const int p = s_par[root[j]];
-            if (p != root[j]) {
-                root[j] = p;
-                moving = true;
-            }
+            root[j] = (FULL || nxt[j] >= 0) ? s_par[FULL ? nxt[j] : max(nxt[j], 0)] : -1;
+            moving |= root[j] != nxt[j];
         }
+        if (!__any(moving)) break;  // root[] == nxt[], final
     }
 
     // ---- local roots draw the cluster decision; labels and faces to HBM -------
@@ -997,17 +1007,8 @@ k_bond(const InstDesc *__restrict__ descs,
             const int j = jf + m, rr = r0 + j;
             isr[m] = row_ok(j) && vc && root[j] == c + TX * rr;
         }
-        uint32_t dec[4] = {0u, 0u, 0u, 0u};
-        if (bits_dec) {
-#pragma unroll
-            for (int m = 0; m < 4; ++m) {
-                const int j = jf + m, rr = r0 + j;
-                if (!isr[m]) continue;
-                const uint32_t g = gin(gx, row_y(j), row_z(j));
-                const uint32_t base = gin((uint32_t)x0, row_y(j), row_z(j)) >> 5;
-                dec[m] = (s_cw[3 * rr + (int)((g >> 5) - base)] >> (g & 31u)) & 1u;
-            }
-        } else if (__ballot(isr[0] || isr[1] || isr[2] || isr[3])) {
+        uint32_t dec[4] = {0u, 0u, 0u, 0u};  // Potts q > 2: the decisions of the group
+        if (!bits_dec && __ballot(isr[0] || isr[1] || isr[2] || isr[3])) {
             const uint32_t gyf = (uint32_t)(y0 + row_y(jf)), gzf = (uint32_t)(z0 + row_z(jf));
             const uint4 w = philox(make_uint4(gx + uL * ((gyf >> 2) + q4 * gzf), n, (uint32_t)TAG_CLUSTER, rep), key0, key1);
             const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
@@ -1019,8 +1020,9 @@ k_bond(const InstDesc *__restrict__ descs,
             const int j = jf + m, rr = r0 + j;
             if (!row_ok(j)) continue;
             const int ly = row_y(j), lz = row_z(j);
-            const int32_t rg = (int32_t)gidx(root[j] < 0 ? 0 : root[j]);
-            if (vc) g_label[gin(gx, ly, lz)] = isr[m] ? (ROOT_FLAG | dec[m]) : (uint32_t)rg;
+            const int32_t rg = (int32_t)gidx(FULL ? root[j] : max(root[j], 0));
+            const uint32_t dm = bits_dec ? (uint32_t)(s_dm[rr] >> c) & 1u : dec[m];
+            if (vc) (g_label + gin((uint32_t)x0, ly, lz))[c] = isr[m] ? (ROOT_FLAG | dm) : (uint32_t)rg;
             // faces for the global merge: the out side marks a bond across the face
             if (fx) {
                 if (c == ex - 1) fo0[rr] = bit_of(bxg, j) ? rg : -1;
