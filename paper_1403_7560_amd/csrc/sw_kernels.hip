@@ -1093,15 +1093,19 @@ __device__ void reduce_partials(const InstDesc &d, int t, int64_t row)
 // are linked on the global label words, the larger under the smaller, with
 // device-scope atomicMin (Hawick's atomicMin on R[label], retried until it
 // links, so one pass reaches the fixed point).  A cluster crosses a face at
-// many sites with the same pair of tile roots: an LDS hash set of the pairs
-// seen lets only the first such bond make the (global, atomic) union.  The
-// first workgroups of a lattice also reduce the sweep's measurement partials.
+// many sites with the same pair of tile roots, so the pairs are first made
+// unique in an LDS hash set (the face element before each one is compared
+// first, which removes most repeats without touching the set); the thread
+// that inserts a pair links it.  All face elements of the tile are loaded at
+// once, before any link.  The first workgroups of a lattice also reduce the
+// sweep's measurement partials.
 // ---------------------------------------------------------------------------
 template <int DIM>
 __global__ void __launch_bounds__(256) k_merge(const InstDesc *__restrict__ descs,
                                                const int2 *__restrict__ tmap, uint32_t k)
 {
-    constexpr int HB = (DIM == 2) ? 256 : 2048;  // hash slots (about 2x the face elements)
+    constexpr int HB = (DIM == 2) ? 256 : 2048;  // hash slots (at least the face elements)
+    constexpr int EMAX = (DIM == 2) ? 1 : 7;     // face elements per thread (all tile shapes)
     constexpr unsigned long long EMPTY = ~0ull;
     __shared__ unsigned long long s_set[HB];
     const int2 tm = tmap[tile_slot()];
@@ -1119,45 +1123,83 @@ __global__ void __launch_bounds__(256) k_merge(const InstDesc *__restrict__ desc
     }
     uint32_t *lab = labels_of(d, d.sweep0 + k);
     for (int h = tid; h < HB; h += 256) s_set[h] = EMPTY;
-    __syncthreads();
+    // the faces with a neighbour tile, one after the other in element order
     const int tc[3] = {t % d.tiles[0], (t / d.tiles[0]) % d.tiles[1],
                        (DIM == 3) ? t / (d.tiles[0] * d.tiles[1]) : 0};
+    const GLOBAL int32_t *fo[DIM], *fi[DIM];
+    int fend[DIM];  // end of face mu in element order
+    int total = 0;
 #pragma unroll
     for (int mu = 0; mu < DIM; ++mu) {
-        if (d.tiles[mu] == 1) continue;
-        const int F = d.face_len[mu];
+        const int F = d.tiles[mu] > 1 ? d.face_len[mu] : 0;
         int cn[3] = {tc[0], tc[1], tc[2]};
         cn[mu] = (cn[mu] + 1 == d.tiles[mu]) ? 0 : cn[mu] + 1;
         const int nb = cn[0] + d.tiles[0] * (cn[1] + d.tiles[1] * cn[2]);
-        const GLOBAL int32_t *fo = (const GLOBAL int32_t *)d.face + d.face_off[mu] + (int64_t)t * 2 * F;
-        const GLOBAL int32_t *fi = (const GLOBAL int32_t *)d.face + d.face_off[mu] + (int64_t)nb * 2 * F + F;
-        for (int k0 = 0; k0 < F; k0 += 256) {
-            const int kk = k0 + tid;
-            const int32_t a = (kk < F) ? fo[kk] : -1;
-            const int32_t b = (kk < F && a >= 0) ? fi[kk] : -1;
-            // the previous face element (lane - 1; lane 0 loads it) with the
-            // same pair makes this union
-            int32_t pa = (int32_t)from_left((uint32_t)a), pb = (int32_t)from_left((uint32_t)b);
-            if ((tid & 63) == 0 && kk > 0 && kk < F) {
-                pa = fo[kk - 1];
-                pb = (pa >= 0) ? fi[kk - 1] : -1;
-            }
-            if (a < 0) continue;
-            if (kk > 0 && pa == a && pb == b) continue;
-            const unsigned long long key = ((unsigned long long)(uint32_t)a << 32) | (uint32_t)b;
-            uint32_t h = ((uint32_t)a * 0x9E3779B1u) ^ ((uint32_t)b * 0x85EBCA77u);
-            bool fresh = true;
-            for (int probe = 0; probe < 8; ++probe) {
-                h = (h + (uint32_t)probe) & (HB - 1);
-                const unsigned long long old = atomicCAS(&s_set[h], EMPTY, key);
-                if (old == EMPTY) break;  // inserted: this thread links the pair
-                if (old == key) {
-                    fresh = false;  // seen before in this tile
-                    break;
+        fo[mu] = (const GLOBAL int32_t *)d.face + d.face_off[mu] + (int64_t)t * 2 * d.face_len[mu];
+        fi[mu] = (const GLOBAL int32_t *)d.face + d.face_off[mu] + (int64_t)nb * 2 * d.face_len[mu] +
+                 d.face_len[mu];
+        total += F;
+        fend[mu] = total;
+    }
+    // element e: face mu, position kk; out side a (-1: no bond), in side b
+    int32_t a[EMAX], b[EMAX], pa[EMAX], pb[EMAX];
+    bool first[EMAX];
+#pragma unroll
+    for (int i = 0; i < EMAX; ++i) {
+        const int e = tid + 256 * i;
+        a[i] = b[i] = pa[i] = pb[i] = -1;
+        first[i] = true;
+        if (e < total) {
+            int mu = 0, start = 0;
+#pragma unroll
+            for (int m = 0; m + 1 < DIM; ++m)
+                if (e >= fend[m]) {
+                    mu = m + 1;
+                    start = fend[m];
                 }
+            const int kk = e - start;
+            const GLOBAL int32_t *po = fo[0], *pi = fi[0];
+#pragma unroll
+            for (int m = 1; m < DIM; ++m)
+                if (mu == m) {
+                    po = fo[m];
+                    pi = fi[m];
+                }
+            a[i] = po[kk];
+            b[i] = pi[kk];
+            first[i] = kk == 0;
+            // lane 0 loads the element before it; the other lanes take their
+            // left neighbour's below
+            if ((tid & 63) == 0 && kk > 0) {
+                pa[i] = po[kk - 1];
+                pb[i] = pi[kk - 1];
             }
-            if (fresh) gunion(lab, (uint32_t)a, (uint32_t)b);
         }
+    }
+    __syncthreads();  // hash set cleared
+#pragma unroll
+    for (int i = 0; i < EMAX; ++i) {
+        if (256 * i >= total) break;  // uniform
+        const int32_t la = (int32_t)from_left((uint32_t)a[i]), lb = (int32_t)from_left((uint32_t)b[i]);
+        if ((tid & 63) != 0) {
+            pa[i] = la;
+            pb[i] = lb;
+        }
+        if (a[i] < 0) continue;
+        if (!first[i] && pa[i] == a[i] && pb[i] == b[i]) continue;  // same pair as the element before
+        const unsigned long long key = ((unsigned long long)(uint32_t)a[i] << 32) | (uint32_t)b[i];
+        uint32_t h = ((uint32_t)a[i] * 0x9E3779B1u) ^ ((uint32_t)b[i] * 0x85EBCA77u);
+        bool fresh = true;
+        for (int probe = 0; probe < 8; ++probe) {
+            h = (h + (uint32_t)probe) & (HB - 1);
+            const unsigned long long old = atomicCAS(&s_set[h], EMPTY, key);
+            if (old == EMPTY) break;  // inserted: this thread links the pair
+            if (old == key) {
+                fresh = false;  // seen before in this tile
+                break;
+            }
+        }
+        if (fresh) gunion(lab, (uint32_t)a[i], (uint32_t)b[i]);
     }
 }
 
