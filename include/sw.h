@@ -142,12 +142,13 @@ void sw_destroy(sw_handle h);
 /* Message of the last error on the calling thread ("" if none). */
 const char *sw_last_error(void);
 
-/* Per-kernel device time.  Level 1 brackets every launch of the bond kernel
- * (bond generation + tile labelling; for Ising and Potts it also applies the
- * previous sweep's cluster decisions) with HIP events on the handle's stream
- * and accumulates its duration; level 2 also times the label merge across
- * tiles (more events, so a little slower); 0 turns it off.  Any level > 0
- * clears the totals.  SW_E_INVALID for other levels. */
+/* Per-kernel device time of plain sweeps.  Level 1 brackets the bond kernel
+ * (bond generation + tile labelling; it also applies the previous sweep's
+ * cluster decisions) of every sweep whose index is a multiple of 16 with HIP
+ * events on the handle's stream and accumulates its duration and the number
+ * of launches timed; level 2 also times those sweeps' label merge across
+ * tiles; 0 turns it off.  Any level > 0 clears the totals.  SW_E_INVALID for
+ * other levels. */
 int sw_profile(sw_handle h, int on);
 /* Accumulated milliseconds and launch counts per kernel (3 entries each:
  * 0 = bond, 1 = merge, 2 = flip; the flip is not timed and stays 0). */

@@ -193,7 +193,7 @@ class Lattice:
         return out
 
     def profile(self, level):
-        """0 off; 1 time every bond-kernel launch; 2 time all three kernels."""
+        """0 off; 1 time the bond kernel of every 16th sweep; 2 also its merge."""
         _check(lib().sw_profile(self.h, int(level)))
 
     def profile_read(self):

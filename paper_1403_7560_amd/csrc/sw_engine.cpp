@@ -112,7 +112,10 @@ struct Lattice {
     int2 *d_tmap = nullptr;      // tile map for solo sweeps
     hipStream_t stream = nullptr;
     // per-kernel event timing
-    int profiling = 0;  // 1: events around k_bond; 2: around all three kernels
+    int profiling = 0;  // 1: events around k_bond; 2: also around k_merge
+    // events bracket the launches of every PROFILE_EVERY-th sweep only: an
+    // event pair around every launch would slow the sweep it measures
+    static constexpr int64_t PROFILE_EVERY = 16;
     std::vector<hipEvent_t> events;
     double prof_ms[3] = {0, 0, 0};
     int64_t prof_n[3] = {0, 0, 0};
@@ -303,14 +306,18 @@ struct Lattice {
             d.count = (uint32_t)m;
             HIPCHK(hipMemcpyAsync(d_solo, &d, sizeof(d), hipMemcpyHostToDevice, stream));
             HIPCHK(hipStreamSynchronize(stream));
+            // timed sweeps: those whose index is a multiple of PROFILE_EVERY
+            const int64_t first_timed = (PROFILE_EVERY - sweep % PROFILE_EVERY) % PROFILE_EVERY;
+            const int64_t ntimed = first_timed < m ? (m - 1 - first_timed) / PROFILE_EVERY + 1 : 0;
             if (profiling) {
-                int rc = ensure_events((size_t)(4 * m));
+                int rc = ensure_events((size_t)(4 * std::max<int64_t>(ntimed, 1)));
                 if (rc) return rc;
             }
             // each sweep's bond kernel applies the previous sweep's cluster
             // decisions; the chain's last decisions are applied once at the end
             for (int64_t k = 0; k < m; ++k) {
-                hipEvent_t *ev = profiling ? &events[(size_t)(4 * k)] : nullptr;
+                const bool timed = profiling && k >= first_timed && (k - first_timed) % PROFILE_EVERY == 0;
+                hipEvent_t *ev = timed ? &events[(size_t)(4 * ((k - first_timed) / PROFILE_EVERY))] : nullptr;
                 if (ev) HIPCHK(hipEventRecord(ev[0], stream));
                 HIPCHK(launch_bond(model, dim, variant, d_solo, d_tmap, ntiles, nfull, (uint32_t)k, 0, stream));
                 if (ev) HIPCHK(hipEventRecord(ev[1], stream));
@@ -321,7 +328,7 @@ struct Lattice {
             HIPCHK(hipStreamSynchronize(stream));
             if (profiling) {
                 const int nk = profiling > 1 ? 2 : 1;
-                for (int64_t k = 0; k < m; ++k) {
+                for (int64_t k = 0; k < ntimed; ++k) {
                     for (int c = 0; c < nk; ++c) {
                         float ms = 0.f;
                         HIPCHK(hipEventElapsedTime(&ms, events[(size_t)(4 * k + c)], events[(size_t)(4 * k + c + 1)]));

@@ -169,6 +169,20 @@ def test_sweeps_split_across_calls():
     compare_records(ISING, 2, 80, 2, lat.series(), ref["records"])
 
 
+def test_profiling_times_every_16th_sweep_and_changes_nothing():
+    say("[profile] Ising 2D L=130, sweeps 5..44 timed, then compared with the oracle")
+    lat = sw.Lattice(ISING, 2, 130, 2, 0.44, 21)
+    lat.sweep(5)
+    lat.profile(2)
+    lat.sweep(40)  # sweep indices 5..44: 16 and 32 are timed
+    p = lat.profile_read()
+    lat.profile(0)
+    assert p["bond"][1] == 2 and p["merge"][1] == 2 and p["flip"][1] == 0
+    assert p["bond"][0] > 0.0 and p["merge"][0] > 0.0
+    ref = oracle.sweeps(ISING, 2, 130, 2, 0.44, 21, 0, 0, 45, oracle.init_state(ISING, 2, 130, 2, 21))
+    compare_lattice(ISING, lat.get_state(), lat.get_labels(), lat.get_bonds(), ref)
+
+
 @pytest.mark.parametrize("beta", [0.0, 50.0])
 def test_degenerate_couplings(beta):
     """beta = 0: no bond is active, every site is its own cluster.
