@@ -45,11 +45,11 @@ DESCRIPTION = {
 
 
 def algorithmic_bytes_per_site(model):
-    # XY k_bond: read the angle, write the bond byte and the int32 label.
-    # Ising / Potts k_bond also applies the previous sweep's cluster
-    # decisions: it reads the previous sweep's int32 label instead of the
-    # state byte, then writes the bond byte and the int32 label.
-    return 4 + 1 + 4
+    # k_bond applies the previous sweep's cluster decisions as it reads the
+    # incoming configuration: it reads the previous sweep's int32 label and
+    # writes the bond byte and the new int32 label; XY also reads the
+    # previous working angle and writes the new one (FP32).
+    return 4 + 1 + 4 + (8 if model == 2 else 0)
 
 
 def kernel_source_hash():
