@@ -100,7 +100,7 @@ def served(n_jobs, rate, seed=2014):
     from paper_1403_7560_amd import inputs
     jobs = inputs.job_mix(n_jobs, rate=rate, seed=seed)
     updates = sum(j["L"] ** j["dim"] * j["sweeps"] for j in jobs)
-    srv = sw.Server(96 << 30, max_active=128, chunk=32)
+    srv = sw.Server(96 << 30, max_active=256, chunk=32)
     lat_s = np.zeros(n_jobs)
     finish = np.zeros(n_jobs)
     info = {}

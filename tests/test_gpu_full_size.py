@@ -1,0 +1,56 @@
+"""GPU parity at the workloads' full sizes, in the launch configuration
+bench.py times: 2D q=3 Potts and 2D Ising at L = 4096 and 3D Ising at
+L = 256 in the plain form (one lattice per launch), 3D XY at L = 128 as 32
+replicas in one batched launch.  Two sweeps each (the second applies the
+first one's cluster decisions inside the bond kernel); every site's state,
+label and bond byte and every record is compared with the oracle, which
+finishes a full-size sweep in a few seconds."""
+import sys
+
+import pytest
+
+import oracle
+from paper_1403_7560_amd import inputs
+
+sw = pytest.importorskip("paper_1403_7560_amd")
+pytestmark = pytest.mark.gpu
+
+from test_gpu_parity import compare_lattice, compare_records  # noqa: E402
+
+SWEEPS = 2
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def oracle_run(j, n):
+    s0 = oracle.init_state(j["model"], j["dim"], j["L"], j["q"], j["seed"], j["replica"])
+    return oracle.sweeps(j["model"], j["dim"], j["L"], j["q"], j["beta"], j["seed"], j["replica"], 0, n, s0)
+
+
+@pytest.mark.parametrize("name", ["C2-potts", "C2-ising", "C3"])
+def test_plain_form_full_size(name):
+    (j,), _ = inputs.workload(name)
+    say(f"[full] {name}: model={j['model']} dim={j['dim']} L={j['L']} sweeps={SWEEPS}")
+    lat = sw.Lattice(j["model"], j["dim"], j["L"], j["q"], j["beta"], j["seed"], j["replica"])
+    lat.sweep(SWEEPS)
+    ref = oracle_run(j, SWEEPS)
+    compare_lattice(j["model"], lat.get_state(), lat.get_labels(), lat.get_bonds(), ref)
+    compare_records(j["model"], j["dim"], j["L"], j["q"], lat.series(), ref["records"])
+    lat.close()
+
+
+def test_batched_form_full_size():
+    lats, _ = inputs.workload("C4")
+    say(f"[full] C4: {len(lats)} XY 3D L={lats[0]['L']} replicas in one batch, sweeps={SWEEPS}")
+    b = sw.Batch(lats)
+    b.sweep(SWEEPS)
+    for r in (0, 13, len(lats) - 1):
+        j, m = lats[r], b.members[r]
+        say(f"[full] C4 replica {r} T={1.0 / j['beta']:.5f}")
+        ref = oracle_run(j, SWEEPS)
+        compare_lattice(j["model"], m.get_state(), m.get_labels(), m.get_bonds(), ref)
+        compare_records(j["model"], j["dim"], j["L"], j["q"], m.series(), ref["records"])
+    b.close()

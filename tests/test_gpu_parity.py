@@ -73,6 +73,8 @@ CASES = [
     (ISING, 3, 3, 2, 4.5115, 20),
     (ISING, 3, 33, 2, 4.5115, 5),
     (ISING, 3, 40, 2, 4.0, 4),
+    (ISING, 3, 72, 2, 4.5115, 3),  # interior tiles of every 3D shape
+    (POTTS, 3, 66, 3, 1.6, 2),
     (POTTS, 3, 17, 3, 1.8, 5),
     (POTTS, 3, 34, 4, 1.6, 3),
     (XY, 2, 5, 0, 0.89, 15),
@@ -81,6 +83,7 @@ CASES = [
     (XY, 3, 3, 0, 2.2019, 15),
     (XY, 3, 18, 0, 2.2019, 4),
     (XY, 3, 33, 0, 2.0, 3),
+    (XY, 3, 68, 0, 2.2019, 2),  # interior tiles
 ]
 
 
@@ -105,7 +108,9 @@ def test_hot_start_and_sweeps(model, dim, L, q, T, n):
 
 
 TILE_CASES = [(ISING, 2, 150, 2, 2.269185), (POTTS, 2, 99, 4, 0.91), (ISING, 3, 21, 2, 4.5115),
-              (POTTS, 3, 17, 3, 1.8), (XY, 2, 70, 0, 0.9), (XY, 3, 19, 0, 2.2019)]
+              (POTTS, 3, 17, 3, 1.8), (XY, 2, 70, 0, 0.9), (XY, 3, 19, 0, 2.2019),
+              # sides with tiles wholly inside the lattice for every shape
+              (ISING, 2, 300, 2, 2.269185), (ISING, 3, 80, 2, 4.5115), (XY, 3, 72, 0, 2.2019)]
 
 
 @pytest.mark.parametrize("model,dim,L,q,T", TILE_CASES)
