@@ -94,8 +94,11 @@ sw_handle sw_create_replica(int model, int dim, int L, int q, double beta, uint6
 
 /* As sw_create_replica on an explicit tile shape: tile in [0, sw_tile_count)
  * picks the shape of the labelling tiles (Sec. 2, step (2): the local pass
- * works on one tile in on-chip memory), -1 the tuned or default shape.  The
- * shape changes the speed, never the trajectory.  NULL on error. */
+ * works on one tile in on-chip memory), -1 the shape sw_tune recorded for
+ * (model, dim, L), else shape 0 (the fastest on large lattices) unless
+ * another shape pads the lattice to whole tiles by more than a quarter less
+ * (then the one that pads least).  The shape changes the speed, never the
+ * trajectory.  NULL on error. */
 sw_handle sw_create_tiled(int model, int dim, int L, int q, double beta, uint64_t seed,
                           uint32_t replica, int tile);
 

@@ -487,11 +487,37 @@ static hipStream_t make_stream()
 static std::mutex g_tune_mu;
 static std::map<std::tuple<int, int, int>, int> g_tuned;
 
+// Shape of a lattice nobody has tuned: the first of the table (the fastest on
+// large lattices) unless padding the lattice to whole tiles of it costs more
+// than a quarter over the shape that pads least.
+static int default_tile(int model, int dim, int L)
+{
+    auto padded = [&](int v) {
+        const TileShape s = tile_shape(model, dim, v);
+        const int e[3] = {s.tx, s.ty, dim == 3 ? s.tz : 1};
+        int64_t p = 1;
+        for (int mu = 0; mu < dim; ++mu) {
+            if (e[mu] <= 0) return INT64_MAX;  // no such shape
+            p *= (int64_t)((L + e[mu] - 1) / e[mu]) * e[mu];
+        }
+        return p;
+    };
+    if (num_tile_variants(model, dim) <= 0 || L <= 0) return 0;
+    int best = 0;
+    int64_t pmin = padded(0);
+    for (int v = 1; v < num_tile_variants(model, dim); ++v)
+        if (padded(v) < pmin) {
+            best = v;
+            pmin = padded(v);
+        }
+    return padded(0) * 4 <= pmin * 5 ? 0 : best;
+}
+
 static int tuned_tile(int model, int dim, int L)
 {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tuned.find(std::make_tuple(model, dim, L));
-    return it == g_tuned.end() ? 0 : it->second;
+    return it == g_tuned.end() ? default_tile(model, dim, L) : it->second;
 }
 
 // ---------------------------------------------------------------------------
@@ -830,6 +856,7 @@ sw_handle sw_create_tiled(int model, int dim, int L, int q, double beta, uint64_
                           int tile)
 {
     g_err.clear();
+    if (validate(model, dim, L, q, beta)) return nullptr;  // before any use of the shape tables
     if (tile < -1 || (tile >= 0 && tile >= num_tile_variants(model, dim))) {
         fail(SW_E_INVALID, "unknown tile shape");
         return nullptr;

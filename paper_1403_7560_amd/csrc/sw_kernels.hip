@@ -153,9 +153,14 @@ __device__ __noinline__ void flush_queue(lds_int *par, const lds_u32 *q, int qn,
 }
 
 // ---- union-find on the global label words -----------------------------------
+// The finds read label words without device-wide coherence (an XCD's L2 may
+// hold an older value).  That is safe: a word only ever moves to a smaller
+// index of the same cluster, so an old value is still an ancestor, and the
+// atomicMin that links roots is device-scope and returns the current word,
+// from which the union continues.
 __device__ __forceinline__ uint32_t glabel_load(uint32_t *p)
 {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 __device__ __forceinline__ void glabel_store(uint32_t *p, uint32_t v)
@@ -375,28 +380,30 @@ __device__ __forceinline__ uint32_t xy_bond_fast(double two_beta, double si, dou
 template <int MODEL> struct LaneValue { typedef uint32_t type; };
 template <> struct LaneValue<XY> { typedef double type; };
 
-// Workgroups per CU the bond kernel is register-limited to: Ising / Potts as
-// many as its LDS allows (160 KB per CU), up to the 8 waves per SIMD of the
-// hardware; XY keeps its FP64 projections in registers and runs 4.
-template <int MODEL, int T> struct BondOccupancy {
-    static constexpr int value = (MODEL == XY) ? 4 : ((T <= 4096) ? 8 : 3);
+// Wavefronts per SIMD the bond kernel's registers are sized for: Ising /
+// Potts the hardware's 8 while a wavefront holds at most 16 rows (the LDS
+// of 8 such wavefronts per SIMD fits the CU's 160 KB), else 3; XY keeps its
+// FP64 projections in registers and runs 4.
+template <int MODEL, int T, int NW> struct BondOccupancy {
+    static constexpr int value = (MODEL == XY) ? 4 : ((T / NW <= 1024) ? 8 : 3);
 };
 
-template <int MODEL, int DIM, int TX, int TY, int TZ, bool FULL>
-__global__ void __launch_bounds__(256, (BondOccupancy<MODEL, TX * TY * TZ>::value))
+template <int MODEL, int DIM, int TX, int TY, int TZ, int NW, bool FULL>
+__global__ void __launch_bounds__(64 * NW, (BondOccupancy<MODEL, TX * TY * TZ, NW>::value))
 k_bond(const InstDesc *__restrict__ descs,
                                               const int2 *__restrict__ tmap, uint32_t k, int mode)
 {
     typedef typename StateOf<MODEL>::type S;
     constexpr int T = TX * TY * TZ;
     constexpr int ROWS = TY * TZ;
-    constexpr int R = ROWS / 4;  // rows per wavefront
+    constexpr int NT = 64 * NW;  // threads per workgroup (NW wavefronts)
+    constexpr int R = ROWS / NW; // rows per wavefront
     constexpr int NG = R / 4;    // groups of four rows per wavefront
     constexpr bool IS_XY = (MODEL == XY);
     constexpr int QCAP = 128;    // per-wave queue of deferred equivalences
     constexpr int NONE = 0x7fffffff;
     static_assert(TX == 64, "a tile row is one wavefront (lane = column)");
-    static_assert(R % 4 == 0 && R <= 32, "whole row groups, one bond bit per row");
+    static_assert(ROWS % NW == 0 && R % 4 == 0 && R <= 32, "whole row groups, one bond bit per row");
     static_assert(TY % 4 == 0, "row groups of the column random layout stay in a plane");
     static_assert(DIM == 2 ? TZ == 1 : R % TY == 0, "3D: whole planes per wavefront");
 
@@ -404,12 +411,12 @@ k_bond(const InstDesc *__restrict__ descs,
     __shared__ unsigned long long s_xm[ROWS];  // in-tile x-bond mask of every row
     __shared__ uint32_t s_rowg[ROWS];          // global index of every row's first site
     __shared__ unsigned long long s_dm[ROWS];  // cluster decision bit of every site, one word per row
-    __shared__ uint32_t s_q[4][QCAP];
+    __shared__ uint32_t s_q[NW][QCAP];
     // Potts histogram of the measurement: it is done before the scan fills the
     // equivalence queues, so it shares their memory
     int *s_hist = (int *)&s_q[0][0];
-    static_assert(4 * QCAP >= 256, "histogram fits the queues");
-    __shared__ double s_red[4][3];
+    static_assert(NW * QCAP >= 256, "histogram fits the queues");
+    __shared__ double s_red[NW][3];
     __shared__ double s_phi[4];  // XY: phi, cos phi, sin phi, previous sweep's phi
     __shared__ double2 s_cs[IS_XY ? XY_TAB : 1];  // XY: cos/sin(k 2pi/128)
 
@@ -488,8 +495,8 @@ k_bond(const InstDesc *__restrict__ descs,
         s_phi[3] = from_labels ? xy_phi(d, n - 1u) : 0.0;
     }
     if (MODEL == POTTS && meas)
-        for (int q = tid; q < d.q; q += 256) s_hist[q] = 0;
-    for (int r = tid; r < ROWS; r += 256) s_rowg[r] = gat((uint32_t)x0, r % TY, r / TY);
+        for (int q = tid; q < d.q; q += NT) s_hist[q] = 0;
+    for (int r = tid; r < ROWS; r += NT) s_rowg[r] = gat((uint32_t)x0, r % TY, r / TY);
     // Cluster decision bits of every tile row (one bit per possible root): bit
     // c of s_dm[r] is bit g mod 32 of word g/32 of the cluster stream, g the
     // global index of site (x0 + c, row r).  The row's 64 bits lie in three
@@ -864,18 +871,19 @@ k_bond(const InstDesc *__restrict__ descs,
         }
         __syncthreads();
         if (tid == 0) {
+            // wavefronts in order (a fixed order: deterministic XY sums)
+            double v[3] = {0.0, 0.0, 0.0};
+            for (int w = 0; w < NW; ++w)
+                for (int q = 0; q < 3; ++q) v[q] += s_red[w][q];
             if (IS_XY) {
-                for (int q = 0; q < 3; ++q) {
-                    const double v = ((s_red[0][q] + s_red[1][q]) + s_red[2][q]) + s_red[3][q];
-                    part[q] = __double_as_longlong(v);
-                }
+                for (int q = 0; q < 3; ++q) part[q] = __double_as_longlong(v[q]);
             } else {
-                part[0] = (int64_t)(s_red[0][0] + s_red[1][0] + s_red[2][0] + s_red[3][0]);
-                if (MODEL == ISING) part[1] = (int64_t)(s_red[0][1] + s_red[1][1] + s_red[2][1] + s_red[3][1]);
+                part[0] = (int64_t)v[0];
+                if (MODEL == ISING) part[1] = (int64_t)v[1];
             }
         }
         if (MODEL == POTTS)
-            for (int q = tid; q < d.q; q += 256) part[1 + q] = s_hist[q];
+            for (int q = tid; q < d.q; q += NT) part[1 + q] = s_hist[q];
     }
     if (!full) return;
 
@@ -1100,12 +1108,12 @@ __device__ void reduce_partials(const InstDesc &d, int t, int64_t row)
 // once, before any link.  The first workgroups of a lattice also reduce the
 // sweep's measurement partials.
 // ---------------------------------------------------------------------------
-template <int DIM>
+template <int DIM, int EMAX>
 __global__ void __launch_bounds__(256) k_merge(const InstDesc *__restrict__ descs,
                                                const int2 *__restrict__ tmap, uint32_t k)
 {
-    constexpr int HB = (DIM == 2) ? 256 : 2048;  // hash slots (at least the face elements)
-    constexpr int EMAX = (DIM == 2) ? 1 : 7;     // face elements per thread (all tile shapes)
+    // EMAX: face elements per thread (the tile shape's faces over 256 threads)
+    constexpr int HB = (DIM == 2) ? 512 : 2048;  // hash slots (about the face elements with a bond)
     constexpr unsigned long long EMPTY = ~0ull;
     __shared__ unsigned long long s_set[HB];
     const int2 tm = tmap[tile_slot()];
@@ -1226,13 +1234,13 @@ __global__ void __launch_bounds__(256) k_reduce(const InstDesc *__restrict__ des
 // lock-step rounds, and the final root is written back into the tile root
 // so that later workgroups take one hop.
 // ---------------------------------------------------------------------------
-template <int MODEL, int DIM, int TX, int TY, int TZ>
-__global__ void __launch_bounds__(256, (MODEL == XY) ? 4 : 8) k_flip(const InstDesc *__restrict__ descs,
+template <int MODEL, int DIM, int TX, int TY, int TZ, int NW>
+__global__ void __launch_bounds__(64 * NW, (MODEL == XY) ? 4 : 8) k_flip(const InstDesc *__restrict__ descs,
                                               const int2 *__restrict__ tmap, uint32_t k)
 {
     constexpr int ROWS = TY * TZ;
-    constexpr int R = ROWS / 4;
-    static_assert(TX == 64 && ROWS % 4 == 0, "lane = column, whole rows per wavefront");
+    constexpr int R = ROWS / NW;
+    static_assert(TX == 64 && ROWS % NW == 0, "lane = column, whole rows per wavefront");
     __shared__ double s_phi;
     const int2 tm = tmap[tile_slot()];
     if (tm.x < 0) return;
@@ -1355,18 +1363,30 @@ __global__ void k_advance(InstDesc *descs, int ninst)
 }
 
 // ---------------------------------------------------------------------------
-// Variant table and launchers.
+// Variant table and launchers: X(variant, TX, TY, TZ, wavefronts per workgroup).
+// The first shape of each table is the fastest on large lattices (it is the
+// default unless it pads a small lattice much more than another shape).
 // ---------------------------------------------------------------------------
-#define SW_VARIANTS_ISING2 X(0, 64, 64, 1) X(1, 64, 32, 1) X(2, 64, 128, 1)
-#define SW_VARIANTS_ISING3 X(0, 64, 8, 8) X(1, 64, 4, 8) X(2, 64, 8, 16)
-#define SW_VARIANTS_XY2 X(0, 64, 32, 1) X(1, 64, 16, 1) X(2, 64, 64, 1)
-#define SW_VARIANTS_XY3 X(0, 64, 4, 8) X(1, 64, 8, 4) X(2, 64, 4, 4)
+#define SW_VARIANTS_ISING2 X(0, 64, 64, 1, 4) X(1, 64, 32, 1, 4) X(2, 64, 128, 1, 8) X(3, 64, 256, 1, 16)
+#define SW_VARIANTS_ISING3 X(0, 64, 8, 16, 8) X(1, 64, 8, 8, 4) X(2, 64, 4, 8, 4) X(3, 64, 16, 16, 16)
+#define SW_VARIANTS_XY2 X(0, 64, 32, 1, 4) X(1, 64, 16, 1, 4) X(2, 64, 64, 1, 8)
+#define SW_VARIANTS_XY3 X(0, 64, 4, 8, 4) X(1, 64, 8, 4, 4) X(2, 64, 8, 8, 8) X(3, 64, 8, 16, 16)
 
-int num_tile_variants(int, int) { return 3; }
+int num_tile_variants(int model, int dim)
+{
+    int n = 0;
+#define X(i, a, b, c, w) ++n;
+    if (model != XY && dim == 2) { SW_VARIANTS_ISING2 }
+    if (model != XY && dim == 3) { SW_VARIANTS_ISING3 }
+    if (model == XY && dim == 2) { SW_VARIANTS_XY2 }
+    if (model == XY && dim == 3) { SW_VARIANTS_XY3 }
+#undef X
+    return n;
+}
 
 TileShape tile_shape(int model, int dim, int v)
 {
-#define X(i, a, b, c) \
+#define X(i, a, b, c, w) \
     if (v == i) return TileShape{a, b, c};
     if (model != XY && dim == 2) { SW_VARIANTS_ISING2 }
     if (model != XY && dim == 3) { SW_VARIANTS_ISING3 }
@@ -1399,13 +1419,14 @@ template <int MODEL, int DIM>
 static hipError_t bond_dispatch(int v, const InstDesc *dd, const int2 *tm, int nt, int nf, uint32_t k, int mode,
                                 hipStream_t s)
 {
-#define X(i, a, b, c)                                                                                          \
+#define X(i, a, b, c, w)                                                                                       \
     if (v == i) {                                                                                              \
         if (nf > 0)                                                                                            \
-            hipLaunchKernelGGL((k_bond<MODEL, DIM, a, b, c, true>), dim3(nf), dim3(256), 0, s, dd, tm, k, mode); \
+            hipLaunchKernelGGL((k_bond<MODEL, DIM, a, b, c, w, true>), dim3(nf), dim3(64 * w), 0, s, dd, tm, k,  \
+                               mode);                                                                          \
         if (nt > nf)                                                                                           \
-            hipLaunchKernelGGL((k_bond<MODEL, DIM, a, b, c, false>), dim3(nt - nf), dim3(256), 0, s, dd, tm + nf, \
-                               k, mode);                                                                       \
+            hipLaunchKernelGGL((k_bond<MODEL, DIM, a, b, c, w, false>), dim3(nt - nf), dim3(64 * w), 0, s, dd,   \
+                               tm + nf, k, mode);                                                              \
         return hipGetLastError();                                                                              \
     }
     if constexpr (MODEL != XY && DIM == 2) { SW_VARIANTS_ISING2 }
@@ -1419,10 +1440,10 @@ static hipError_t bond_dispatch(int v, const InstDesc *dd, const int2 *tm, int n
 template <int MODEL, int DIM>
 static hipError_t flip_dispatch(int v, const InstDesc *dd, const int2 *tm, int nt, uint32_t k, hipStream_t s)
 {
-#define X(i, a, b, c)                                                                         \
-    if (v == i) {                                                                             \
-        hipLaunchKernelGGL((k_flip<MODEL, DIM, a, b, c>), dim3(nt), dim3(256), 0, s, dd, tm, k); \
-        return hipGetLastError();                                                             \
+#define X(i, a, b, c, w)                                                                             \
+    if (v == i) {                                                                                    \
+        hipLaunchKernelGGL((k_flip<MODEL, DIM, a, b, c, w>), dim3(nt), dim3(64 * w), 0, s, dd, tm, k); \
+        return hipGetLastError();                                                                    \
     }
     if constexpr (MODEL != XY && DIM == 2) { SW_VARIANTS_ISING2 }
     if constexpr (MODEL != XY && DIM == 3) { SW_VARIANTS_ISING3 }
@@ -1444,15 +1465,30 @@ hipError_t launch_bond(int model, int dim, int v, const InstDesc *dd, const int2
     return dim == 2 ? bond_dispatch<XY, 2>(v, dd, tm, nt, nf, k, mode, s) : bond_dispatch<XY, 3>(v, dd, tm, nt, nf, k, mode, s);
 }
 
+template <int MODEL, int DIM>
+static hipError_t merge_dispatch(int v, const InstDesc *dd, const int2 *tm, int nt, uint32_t k, hipStream_t s)
+{
+    // face elements of a tile: +x face TY TZ, +y face TX TZ, +z face TX TY
+#define X(i, a, b, c, w)                                                                                   \
+    if (v == i) {                                                                                          \
+        constexpr int E = ((b) * (c) + (a) * (c) + (DIM == 3 ? (a) * (b) : 0) + 255) / 256;                \
+        hipLaunchKernelGGL((k_merge<DIM, E>), dim3(nt), dim3(256), 0, s, dd, tm, k);                      \
+        return hipGetLastError();                                                                          \
+    }
+    if constexpr (MODEL != XY && DIM == 2) { SW_VARIANTS_ISING2 }
+    if constexpr (MODEL != XY && DIM == 3) { SW_VARIANTS_ISING3 }
+    if constexpr (MODEL == XY && DIM == 2) { SW_VARIANTS_XY2 }
+    if constexpr (MODEL == XY && DIM == 3) { SW_VARIANTS_XY3 }
+#undef X
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_merge(int dim, int model, int v, const InstDesc *dd, const int2 *tm, int nt, uint32_t k,
                         hipStream_t s)
 {
-    (void)model;
-    (void)v;
     if (nt <= 0) return hipSuccess;
-    if (dim == 2) hipLaunchKernelGGL((k_merge<2>), dim3(nt), dim3(256), 0, s, dd, tm, k);
-    else hipLaunchKernelGGL((k_merge<3>), dim3(nt), dim3(256), 0, s, dd, tm, k);
-    return hipGetLastError();
+    if (model == XY) return dim == 2 ? merge_dispatch<XY, 2>(v, dd, tm, nt, k, s) : merge_dispatch<XY, 3>(v, dd, tm, nt, k, s);
+    return dim == 2 ? merge_dispatch<ISING, 2>(v, dd, tm, nt, k, s) : merge_dispatch<ISING, 3>(v, dd, tm, nt, k, s);
 }
 
 hipError_t launch_reduce(int model, const InstDesc *dd, const int2 *tm, int nt, hipStream_t s)

@@ -92,9 +92,24 @@ def test_tile_shapes_are_host_logic():
             for t in range(n):
                 tx, ty, tz = sw.tile_shape(model, dim, t)
                 assert tx == 64 and ty % 4 == 0 and (tz == 1 if dim == 2 else tz >= 1)
-                assert tx * ty * tz <= 8192
+                assert tx * ty * tz <= 16384
             with pytest.raises(sw.SWError):
                 sw.tile_shape(model, dim, n)
     assert sw.tile_shape(sw.ISING, 2, 0) == (64, 64, 1)
     with pytest.raises(sw.SWError):
         sw.tile_count(3, 2)
+
+
+def test_invalid_lattice_arguments_fail_before_the_device():
+    """Argument checks (and the default tile rule) run before any HIP call:
+    bad arguments raise SW_E_INVALID, with or without a GPU."""
+    import paper_1403_7560_amd as sw
+    for args in [(3, 2, 10, 2), (sw.ISING, 4, 10, 2), (sw.ISING, 2, 2, 2), (sw.POTTS, 2, 10, 1),
+                 (sw.POTTS, 2, 10, 257), (sw.ISING, 3, 1291, 2)]:
+        with pytest.raises(sw.SWError) as e:
+            sw.Lattice(*args, beta=0.4, seed=1)
+        assert e.value.code == -1, args
+    for tile in (-2, 99):
+        with pytest.raises(sw.SWError) as e:
+            sw.Lattice(sw.ISING, 2, 10, 2, beta=0.4, seed=1, tile=tile)
+        assert e.value.code == -1

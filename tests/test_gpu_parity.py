@@ -146,6 +146,24 @@ def test_tuner_picks_a_shape_used_by_later_lattices():
         sw.Lattice(ISING, 2, 64, 2, 0.44, 1, tile=sw.tile_count(ISING, 2))
 
 
+def test_default_tile_shape_follows_padding():
+    """Untuned lattices take shape 0 unless another pads them much less."""
+    def padded(model, dim, L, t):
+        p = 1
+        for e in sw.tile_shape(model, dim, t)[:dim]:
+            p *= -(-L // e) * e
+        return p
+    for model, dim, L in [(ISING, 3, 256), (ISING, 3, 20), (XY, 3, 12), (ISING, 2, 4096), (POTTS, 2, 40)]:
+        say(f"[default tile] model={model} dim={dim} L={L}")
+        lat = sw.Lattice(model, dim, L, 2 if model != XY else 0, 0.3, 3)
+        n = sw.tile_count(model, dim)
+        pads = [padded(model, dim, L, t) for t in range(n)]
+        best = min(range(n), key=lambda t: (pads[t], t))
+        want = 0 if pads[0] * 4 <= pads[best] * 5 else best
+        assert lat.tile == want, (model, dim, L, lat.tile, want, pads)
+        lat.close()
+
+
 @pytest.mark.parametrize("model,dim,L,q,T", [(ISING, 2, 100, 2, 2.3), (POTTS, 3, 20, 5, 1.0),
                                              (XY, 2, 66, 0, 1.1), (XY, 3, 20, 0, 2.2)])
 def test_window_from_generated_state(model, dim, L, q, T):
