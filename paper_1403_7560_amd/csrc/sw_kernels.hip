@@ -664,20 +664,22 @@ k_bond(const InstDesc *__restrict__ descs,
     // +y / +z neighbours of wavefront w's last rows.  Wavefront w + 1 hands
     // them over through LDS, in wavefront w's part of s_par (nodes
     // [64 r0, 64 (r0 + R)), which w writes only once its own scan starts), so
-    // that w neither loads nor resolves them again (Ising / Potts: the packed
-    // states of those row groups).  XY does not: its wavefronts are fewer per
-    // SIMD, and the barrier cost more than the loads it saved.
+    // that w neither loads nor resolves them again (3D Ising / Potts: the
+    // packed states of those row groups).  2D (one row per wavefront) and XY
+    // (fewer wavefronts per SIMD) do not: there the barrier cost more than
+    // the loads it saved.
     constexpr int HG = (DIM == 2) ? 1 : TY / 4;  // row groups handed over
+    constexpr bool HAND = !IS_XY && DIM == 3;
     static_assert(HG <= NG, "the handed-over rows fit the receiving wavefront's nodes");
     if constexpr (!IS_XY) {
 #pragma unroll
         for (int gi = 0; gi < NG; ++gi)
             P[gi] = own[4 * gi] | (own[4 * gi + 1] << 8) | (own[4 * gi + 2] << 16) | (own[4 * gi + 3] << 24);
-        if (wv > 0) {
+        if (HAND && wv > 0) {
 #pragma unroll
             for (int gi = 0; gi < HG; ++gi) s_par[TX * (r0 - R) + TX * gi + c] = (int)P[gi];
         }
-        __syncthreads();
+        if (HAND) __syncthreads();
     }
     // packed states of row group i of the first rows of wavefront wv + 1
     auto handed = [&](int i) -> uint32_t { return (uint32_t)s_par[TX * r0 + TX * i + c]; };
@@ -714,7 +716,6 @@ k_bond(const InstDesc *__restrict__ descs,
                 uint32_t nb;
                 const bool nb_own = DIM == 2 ? (jf + 4 < R && l3 + 1 < ey) : (l3 + 1 < TY && l3 + 1 < ey);
                 if (nb_own) nb = P[gi + 1 < NG ? gi + 1 : gi] & 0xffu;
-                else if (DIM == 2 && l3 + 1 < TY && l3 + 1 < ey) nb = handed(0) & 0xffu;  // wavefront wv + 1
                 else nb = vc ? state_byte(gat(gx, l3 + 1, z3)) : 0u;
                 PU = __builtin_amdgcn_alignbyte(nb, P[gi], 1);
             } else {
@@ -734,7 +735,7 @@ k_bond(const InstDesc *__restrict__ descs,
                 const int lz = row_z(jf);
                 if (jf + TY < R && lz + 1 < ez) {
                     PZ = P[gi + TY / 4 < NG ? gi + TY / 4 : gi];
-                } else if (lz + 1 < TZ && lz + 1 < ez) {
+                } else if (HAND && lz + 1 < TZ && lz + 1 < ez) {
                     PZ = handed((jf % TY) / 4);  // the first plane of wavefront wv + 1
                 } else if (vc) {
 #pragma unroll
