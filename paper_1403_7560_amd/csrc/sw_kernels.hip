@@ -942,7 +942,11 @@ k_bond(const InstDesc *__restrict__ descs,
             const int rr = r0 + j;
             // x bonds to lane c + 1 < ex
             const unsigned long long xb = ballot(bit_of(bxg, j) != 0u) & (vmask >> 1);
-            if (c == 0) s_xm[rr] = xb;
+            // the masks the cross-block and periodic links read (node_of):
+            // full 2D tiles need only each wavefront's first and last row
+            constexpr int HR = (DIM == 2) ? 1 : TY;
+            const bool need_xm = !FULL || j < HR || j >= R - HR || (DIM == 3 && (j % TY == 0 || j % TY == TY - 1));
+            if (need_xm && c == 0) s_xm[rr] = xb;
             const int rs = 63 - __clzll((long long)(~(xb << 1) & upto));
             const int node = rs + TX * rr;
             // bonded to the row above / the plane behind (inside the wavefront's rows)
