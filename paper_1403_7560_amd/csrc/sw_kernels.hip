@@ -567,6 +567,35 @@ k_bond(const InstDesc *__restrict__ descs,
             ownS[j] = 0;
         }
     };
+    // 2D: the merge may have chained this tile's roots of the previous sweep
+    // through other tiles.  Every root of the tile that a face link can have
+    // touched is in the tile's own face slots (the out side's roots with a
+    // bond across, all of the in side's roots); the workgroup first points
+    // each of them at its final root, so that the chase below ends in two
+    // loads for every site.  Only the tile's own slots are read: this launch
+    // overwrites them at its end, while neighbours may already have rewritten
+    // theirs.
+    if (DIM == 2 && from_labels && (d.tiles[0] > 1 || d.tiles[1] > 1)) {
+#pragma unroll
+        for (int mu = 0; mu < 2; ++mu) {
+            if (d.tiles[mu] == 1) continue;  // uniform
+            const int F = d.face_len[mu];
+            const GLOBAL int32_t *fs = (const GLOBAL int32_t *)d.face + d.face_off[mu] + (int64_t)t * 2 * F;
+            for (int e0 = 0; e0 < 2 * F; e0 += NT) {
+                const int e = e0 + tid;
+                const int32_t x = e < 2 * F ? fs[e] : -1;
+                const int32_t xl = (int32_t)from_left((uint32_t)x);
+                if (x < 0 || (c != 0 && xl == x)) continue;  // no root, or the lane before has it
+                uint32_t r = (uint32_t)x, w = lab_prev[r];
+                while (!(w & ROOT_FLAG)) {
+                    r = w;
+                    w = lab_prev[r];
+                }
+                if (r != (uint32_t)x) lab_prev[x] = r;
+            }
+        }
+        __syncthreads();
+    }
     if (from_labels) {
         // per half of the rows: every row's label word, then all their tile
         // roots' words, in flight together; chains the merge made longer walked
