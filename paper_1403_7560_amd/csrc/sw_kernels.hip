@@ -661,6 +661,53 @@ k_bond(const InstDesc *__restrict__ descs,
         V unused;
         return (uint32_t)value_at(g, unused);
     };
+    // incoming values of up to four sites outside this wavefront's rows (those
+    // with use[i]): their previous labels are resolved in lock-step, the first
+    // loads of all four and then their roots' words in flight together, where
+    // value_at walks one chain after the other
+    auto values4 = [&](const uint32_t *g, const bool *use, V *v, V *vs) {
+        if (!from_labels) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                v[i] = 0;
+                vs[i] = 0;
+                if (use[i]) v[i] = value_at(g[i], vs[i]);
+            }
+            return;
+        }
+        uint32_t w[4], val[4];
+        float th[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            w[i] = use[i] ? lab_prev[g[i]] : ROOT_FLAG;
+            th[i] = (IS_XY && use[i]) ? th_prev[g[i]] : 0.0f;
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) val[i] = (w[i] & ROOT_FLAG) ? w[i] : lab_prev[w[i]];
+        bool more = false;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) more |= !(val[i] & ROOT_FLAG);
+        while (more) {
+            more = false;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (!(val[i] & ROOT_FLAG)) {
+                    val[i] = lab_prev[val[i]];
+                    more |= !(val[i] & ROOT_FLAG);
+                }
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            v[i] = 0;
+            vs[i] = 0;
+            if (!use[i]) continue;
+            if constexpr (IS_XY) {
+                xy_sincos((val[i] & 1u) ? xy_reflect(th[i], phi_prev) : th[i], s_cs, v[i], vs[i]);
+            } else {
+                v[i] = (V)state_of_decision<MODEL>(val[i] & 0xffu);
+            }
+        }
+    };
     // halo column: XY: lane j < R holds the site right of the tile in row j;
     // Ising / Potts: lane g < NG holds that column's four rows of group g
     V hx = 0, hxS = 0;
@@ -670,12 +717,19 @@ k_bond(const InstDesc *__restrict__ descs,
         if (ly < ey && lz < ez) hx = value_at(gin(gxr, ly, lz), hxS);
     }
     if (!IS_XY && c < NG) {
+        uint32_t hg[4];
+        bool hu[4];
+        V hv[4], hvs[4];
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
             const int j = 4 * c + m;
             const int ly = DIM == 2 ? r0 + j : j % TY, lz = DIM == 2 ? 0 : r0 / TY + j / TY;
-            if (ly < ey && lz < ez) hxg |= state_byte(gin(gxr, ly, lz)) << (8 * m);
+            hu[m] = ly < ey && lz < ez;
+            hg[m] = hu[m] ? gin(gxr, ly, lz) : 0u;
         }
+        values4(hg, hu, hv, hvs);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) hxg |= (uint32_t)hv[m] << (8 * m);
     }
 
     // ---- (1) bonds and measurement --------------------------------------------
@@ -767,10 +821,17 @@ k_bond(const InstDesc *__restrict__ descs,
                 } else if (HAND && lz + 1 < TZ && lz + 1 < ez) {
                     PZ = handed((jf % TY) / 4);  // the first plane of wavefront wv + 1
                 } else if (vc) {
+                    uint32_t zg[4];
+                    bool zu[4];
+                    V zv[4], zvs[4];
 #pragma unroll
-                    for (int m = 0; m < 4; ++m)
-                        if (row_ok(jf + m))
-                            PZ |= state_byte(gat(gx, row_y(jf + m), lz + 1)) << (8 * m);
+                    for (int m = 0; m < 4; ++m) {
+                        zu[m] = row_ok(jf + m);
+                        zg[m] = zu[m] ? gat(gx, row_y(jf + m), lz + 1) : 0u;
+                    }
+                    values4(zg, zu, zv, zvs);
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) PZ |= (uint32_t)zv[m] << (8 * m);
                 }
             }
             // +x neighbours: lane c + 1, the last column from the halo
@@ -828,6 +889,18 @@ k_bond(const InstDesc *__restrict__ descs,
                 }
             }
         } else {
+            // +z neighbours outside this wavefront's rows, the group's four at once
+            V zbuf[4] = {0, 0, 0, 0}, zbufS[4] = {0, 0, 0, 0};
+            if (DIM == 3 && !(jf + TY < R && row_z(jf) + 1 < ez)) {
+                uint32_t zg[4];
+                bool zu[4];
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    zu[m] = vc && row_ok(jf + m);
+                    zg[m] = zu[m] ? gat(gx, row_y(jf + m), row_z(jf + m) + 1) : 0u;
+                }
+                values4(zg, zu, zbuf, zbufS);
+            }
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
                 const int j = jf + m;
@@ -848,8 +921,9 @@ k_bond(const InstDesc *__restrict__ descs,
                     if (j + TY < R && lz + 1 < ez) {
                         zn = own[j + TY < R ? j + TY : j];
                         znS = ownS[j + TY < R ? j + TY : j];
-                    } else if (vc) {
-                        zn = value_at(gat(gx, ly, lz + 1), znS);
+                    } else {
+                        zn = zbuf[m];
+                        znS = zbufS[m];
                     }
                 }
                 V rt = from_right_d(own[j]), rtS = from_right_d(ownS[j]);
