@@ -321,7 +321,8 @@ struct Lattice {
                 if (ev) HIPCHK(hipEventRecord(ev[0], stream));
                 HIPCHK(launch_bond(model, dim, variant, d_solo, d_tmap, ntiles, nfull, (uint32_t)k, 0, stream));
                 if (ev) HIPCHK(hipEventRecord(ev[1], stream));
-                HIPCHK(launch_merge(dim, model, variant, d_solo, d_tmap, ntiles, (uint32_t)k, stream));
+                // one tile: no faces, and the bond kernel writes the record
+                if (ntiles > 1) HIPCHK(launch_merge(dim, model, variant, d_solo, d_tmap, ntiles, (uint32_t)k, stream));
                 if (ev && profiling > 1) HIPCHK(hipEventRecord(ev[2], stream));
             }
             HIPCHK(launch_flip(model, dim, variant, d_solo, d_tmap, ntiles, FLIP_LAST, stream));

@@ -978,6 +978,11 @@ k_bond(const InstDesc *__restrict__ descs,
     // ---- measurement partials of this tile -----------------------------------
     if (meas) {
         GLOBAL int64_t *part = (GLOBAL int64_t *)d.part + (int64_t)t * d.nslots;
+        // a lattice of one tile has no faces and the plain form launches no
+        // merge for it: the workgroup writes the sweep's record itself (the
+        // merge's reduction of one tile's partials gives the same values)
+        const bool own_rec = full && d.ntiles == 1 && d.rec_row0 >= 0 && d.rec_row0 + (int64_t)k < d.rec_cap;
+        GLOBAL int64_t *rec = (GLOBAL int64_t *)d.rec + (own_rec ? (d.rec_row0 + (int64_t)k) * d.nslots : 0);
         if (IS_XY) {
             const double a = wave_sum_d(e_acc), b = wave_sum_d(sx_acc), cc = wave_sum_d(sy_acc);
             if (c == 0) {
@@ -1000,13 +1005,22 @@ k_bond(const InstDesc *__restrict__ descs,
                 for (int q = 0; q < 3; ++q) v[q] += s_red[w][q];
             if (IS_XY) {
                 for (int q = 0; q < 3; ++q) part[q] = __double_as_longlong(v[q]);
+                if (own_rec)
+                    for (int q = 0; q < 3; ++q) rec[q] = __double_as_longlong(v[q]);
             } else {
                 part[0] = (int64_t)v[0];
                 if (MODEL == ISING) part[1] = (int64_t)v[1];
+                if (own_rec) {
+                    rec[0] = (int64_t)v[0];
+                    if (MODEL == ISING) rec[1] = (int64_t)v[1];
+                }
             }
         }
         if (MODEL == POTTS)
-            for (int q = tid; q < d.q; q += NT) part[1 + q] = s_hist[q];
+            for (int q = tid; q < d.q; q += NT) {
+                part[1 + q] = s_hist[q];
+                if (own_rec) rec[1 + q] = s_hist[q];
+            }
     }
     if (!full) return;
 
