@@ -42,6 +42,9 @@ def workload(name):
         return [dict(model=POTTS, dim=2, L=4096, q=3, beta=1 / tc_potts_2d(3), seed=2, replica=0)], 10000
     if name == "C2-ising":  # 2D Ising L=4096 at the exact Tc
         return [dict(model=ISING, dim=2, L=4096, q=2, beta=1 / TC_ISING_2D, seed=3, replica=0)], 10000
+    if name in ("C2-potts-8192", "C2-ising-8192"):  # the C2 pair at L=8192: larger than the 256 MB Infinity Cache
+        lat, _ = workload(name[:-5])
+        return [dict(lat[0], L=8192)], 2000
     if name == "C3":   # 3D Ising L=256 at T=4.5115
         return [dict(model=ISING, dim=3, L=256, q=2, beta=1 / TC_ISING_3D, seed=4, replica=0)], 2000
     if name == "C4":   # 3D XY L=128, 32 replicas over [0.95 Tc, 1.05 Tc]

@@ -73,6 +73,11 @@ def test_workload_temperatures():
     assert np.allclose(np.diff(T), np.diff(T)[0])
     lats, _ = inputs.workload("C2-potts")
     assert lats[0]["beta"] == pytest.approx(math.log(1 + math.sqrt(3)))
+    for name in ("C2-potts", "C2-ising"):
+        small, _ = inputs.workload(name)
+        big, n = inputs.workload(name + "-8192")
+        assert n == 2000 and big[0]["L"] == 8192
+        assert {k: v for k, v in big[0].items() if k != "L"} == {k: v for k, v in small[0].items() if k != "L"}
 
 
 def test_bench_refuses_several_gpus():
