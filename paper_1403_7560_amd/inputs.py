@@ -33,6 +33,26 @@ def random_state(model, dim, L, q=2, seed=0):
     return th
 
 
+def ordered_state(model, dim, L, q=2, seed=0, disorder=0.05):
+    """A mostly aligned configuration drawn with numpy: every site takes the
+    common state (Ising +1, Potts 0, XY angle 0) except a `disorder` fraction
+    that is drawn uniformly; XY angles also spread by a normal deviate of
+    0.3 rad.  At the workloads' temperatures the bonds of such a state
+    percolate, so the clusters span the lattice as they do once a chain has
+    warmed up near Tc."""
+    rng = np.random.default_rng(seed)
+    N = L ** dim
+    hot = random_state(model, dim, L, q, seed=seed + 1)
+    flip = rng.random(N) < disorder
+    if model == ISING:
+        return np.where(flip, hot, 1).astype(np.int8)
+    if model == POTTS:
+        return np.where(flip, hot, 0).astype(np.uint8)
+    th = np.mod(rng.normal(0.0, 0.3, N), 2 * math.pi).astype(np.float32)
+    th[th >= np.float32(2 * math.pi)] = 0.0
+    return np.where(flip, hot, th).astype(np.float32)
+
+
 # The workloads: (name, list of lattices, sweeps).  A lattice is a dict of
 # model/dim/L/q/beta/seed/replica.
 def workload(name):

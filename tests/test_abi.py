@@ -118,3 +118,19 @@ def test_invalid_lattice_arguments_fail_before_the_device():
         with pytest.raises(sw.SWError) as e:
             sw.Lattice(sw.ISING, 2, 10, 2, beta=0.4, seed=1, tile=tile)
         assert e.value.code == -1
+
+
+def test_ordered_state_recipe():
+    from paper_1403_7560_amd import inputs
+    for model, q, dt in ((0, 2, np.int8), (1, 3, np.uint8), (2, 0, np.float32)):
+        st = inputs.ordered_state(model, 2, 200, q, seed=4)
+        assert st.dtype == dt and st.size == 40000
+        assert np.array_equal(st, inputs.ordered_state(model, 2, 200, q, seed=4))
+        if model == 0:
+            assert set(np.unique(st)) <= {-1, 1} and 0.96 < np.mean(st == 1) < 0.99
+        elif model == 1:
+            assert st.max() < q and 0.95 < np.mean(st == 0) < 0.98
+        else:
+            assert st.min() >= 0 and st.max() < np.float32(2 * math.pi)
+            c = np.mean(np.cos(st.astype(np.float64)))
+            assert 0.85 < c < 0.95  # about (1 - 0.05) * exp(-0.3^2 / 2)

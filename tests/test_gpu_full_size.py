@@ -4,9 +4,13 @@ L = 256 in the plain form (one lattice per launch), 3D XY at L = 128 as 32
 replicas in one batched launch.  Two sweeps each (the second applies the
 first one's cluster decisions inside the bond kernel); every site's state,
 label and bond byte and every record is compared with the oracle, which
-finishes a full-size sweep in a few seconds."""
+finishes a full-size sweep in a few seconds.  Each case runs twice: from
+the hot start (small clusters), and from a seeded, mostly aligned state at
+sweep index 200, the regime of the timed sweeps after the warm-up, where
+one cluster spans the lattice and the global merge links long chains."""
 import sys
 
+import numpy as np
 import pytest
 
 import oracle
@@ -18,6 +22,7 @@ pytestmark = pytest.mark.gpu
 from test_gpu_parity import compare_lattice, compare_records  # noqa: E402
 
 SWEEPS = 2
+N0 = 200  # sweep index of the ordered-state windows
 
 
 def say(*a):
@@ -28,6 +33,17 @@ def say(*a):
 def oracle_run(j, n):
     s0 = oracle.init_state(j["model"], j["dim"], j["L"], j["q"], j["seed"], j["replica"])
     return oracle.sweeps(j["model"], j["dim"], j["L"], j["q"], j["beta"], j["seed"], j["replica"], 0, n, s0)
+
+
+def ordered(j, r=0):
+    return inputs.ordered_state(j["model"], j["dim"], j["L"], j["q"], seed=11 + r)
+
+
+def oracle_window(j, st, n):
+    ref = oracle.sweeps(j["model"], j["dim"], j["L"], j["q"], j["beta"], j["seed"], j["replica"], N0, n, st)
+    # the premise of the case: the last sweep's largest cluster spans the lattice
+    assert np.bincount(ref["labels"]).max() > 0.1 * ref["labels"].size
+    return ref
 
 
 @pytest.mark.parametrize("name", ["C2-potts", "C2-ising", "C3"])
@@ -51,6 +67,40 @@ def test_batched_form_full_size():
         j, m = lats[r], b.members[r]
         say(f"[full] C4 replica {r} T={1.0 / j['beta']:.5f}")
         ref = oracle_run(j, SWEEPS)
+        compare_lattice(j["model"], m.get_state(), m.get_labels(), m.get_bonds(), ref)
+        compare_records(j["model"], j["dim"], j["L"], j["q"], m.series(), ref["records"])
+    b.close()
+
+
+@pytest.mark.parametrize("name", ["C2-potts", "C2-ising", "C3"])
+def test_plain_form_full_size_ordered(name):
+    (j,), _ = inputs.workload(name)
+    say(f"[full-ordered] {name}: model={j['model']} dim={j['dim']} L={j['L']} from sweep {N0}, sweeps={SWEEPS}")
+    st = ordered(j)
+    lat = sw.Lattice(j["model"], j["dim"], j["L"], j["q"], j["beta"], j["seed"], j["replica"])
+    lat.set_state(st)
+    lat.set_sweep_index(N0)
+    lat.sweep(SWEEPS)
+    ref = oracle_window(j, st, SWEEPS)
+    compare_lattice(j["model"], lat.get_state(), lat.get_labels(), lat.get_bonds(), ref)
+    compare_records(j["model"], j["dim"], j["L"], j["q"], lat.series(), ref["records"])
+    lat.close()
+
+
+def test_batched_form_full_size_ordered():
+    lats, _ = inputs.workload("C4")
+    say(f"[full-ordered] C4: {len(lats)} XY 3D L={lats[0]['L']} replicas from sweep {N0}, sweeps={SWEEPS}")
+    b = sw.Batch(lats)
+    states = {}
+    for r, m in enumerate(b.members):
+        states[r] = ordered(lats[r], r)
+        m.set_state(states[r])
+        m.set_sweep_index(N0)
+    b.sweep(SWEEPS)
+    for r in (0, 13, len(lats) - 1):
+        j, m = lats[r], b.members[r]
+        say(f"[full-ordered] C4 replica {r} T={1.0 / j['beta']:.5f}")
+        ref = oracle_window(j, states[r], SWEEPS)
         compare_lattice(j["model"], m.get_state(), m.get_labels(), m.get_bonds(), ref)
         compare_records(j["model"], j["dim"], j["L"], j["q"], m.series(), ref["records"])
     b.close()
