@@ -213,7 +213,8 @@ def test_degenerate_couplings(beta):
     say(f"[degenerate] beta={beta}")
     for model, dim, L, q in [(ISING, 2, 37, 2), (POTTS, 3, 9, 3), (XY, 2, 19, 0)]:
         lat = sw.Lattice(model, dim, L, q, beta, 4)
-        s0 = lat.get_state()
+        s0 = oracle.init_state(model, dim, L, q, 4)
+        assert np.array_equal(lat.get_state().view(np.uint8), s0.view(np.uint8))
         lat.sweep(2)
         ref = oracle.sweeps(model, dim, L, q, beta, 4, 0, 0, 2, s0)
         compare_lattice(model, lat.get_state(), lat.get_labels(), lat.get_bonds(), ref)
@@ -226,7 +227,8 @@ def test_measure_and_cluster_stats():
     for model, dim, L, q, beta in [(ISING, 2, 64, 2, 1 / 2.269185), (POTTS, 3, 12, 3, 0.5)]:
         seed = 31
         lat = sw.Lattice(model, dim, L, q, beta, seed)
-        s0 = lat.get_state()
+        s0 = oracle.init_state(model, dim, L, q, seed)
+        assert np.array_equal(lat.get_state().view(np.uint8), s0.view(np.uint8))
         lat.sweep(10)
         lat.reset_measure()
         lat.sweep(25)
