@@ -737,6 +737,11 @@ k_bond(const InstDesc *__restrict__ descs,
     // (+x, +y, +z): the byte layout of the four-rows-at-once tests below.
     uint32_t bxg[NG], byg[NG], bzg[NG];
     int cnt_al = 0, cnt_m = 0;
+    // Potts, q <= HPACK_Q: this lane's count of every state, 6 bits a state
+    // (a lane holds R < 64 rows), summed over the wavefront at the end
+    constexpr int HPACK_Q = 10;
+    static_assert(R < 64, "state counts are packed in 6-bit fields");
+    unsigned long long hpack = 0ull;
     double e_acc = 0.0, sx_acc = 0.0, sy_acc = 0.0;
     const uint32_t thr_hi = d.thr_hi;
     const uint32_t q4 = (uL + 3u) >> 2;  // column blocks per plane row
@@ -844,6 +849,12 @@ k_bond(const InstDesc *__restrict__ descs,
                 cnt_al += __popc(EQX) + __popc(EQY) + __popc(EQZ);
                 if (MODEL == ISING) {
                     cnt_m += __popc(vb) - 2 * __popc(P[gi] & vb);
+                } else if (d.q <= HPACK_Q) {
+                    // one count per state and group instead of an LDS atomic per
+                    // site: those serialise when a wavefront holds few states
+                    for (int st = 0; st < d.q; ++st)
+                        hpack += (unsigned long long)__popc(zero_bytes(P[gi] ^ (0x01010101u * (uint32_t)st)) & vb)
+                                 << (6 * st);
                 } else {
 #pragma unroll
                     for (int m = 0; m < 4; ++m)
@@ -992,6 +1003,11 @@ k_bond(const InstDesc *__restrict__ descs,
             }
         } else {
             const int a = wave_sum_i(cnt_al), b = wave_sum_i(cnt_m);
+            if (MODEL == POTTS && d.q <= HPACK_Q)
+                for (int st = 0; st < d.q; ++st) {
+                    const int v = wave_sum_i((int)((hpack >> (6 * st)) & 63ull));
+                    if (c == 0) atomicAdd(&s_hist[st], v);
+                }
             if (c == 0) {
                 s_red[wv][0] = (double)a;
                 s_red[wv][1] = (double)b;
