@@ -70,6 +70,8 @@ CASES = [
     (POTTS, 2, 130, 3, 0.994972861, 6),
     (POTTS, 2, 67, 10, 0.701231568, 6),
     (POTTS, 2, 40, 256, 0.3, 4),
+    (POTTS, 2, 50, 2, 1.7, 5),      # q = 2: one-bit decisions, state counts packed
+    (POTTS, 2, 45, 11, 0.7, 4),     # q = 11: the smallest q counted with LDS atomics
     (ISING, 3, 3, 2, 4.5115, 20),
     (ISING, 3, 33, 2, 4.5115, 5),
     (ISING, 3, 40, 2, 4.0, 4),
@@ -77,6 +79,7 @@ CASES = [
     (POTTS, 3, 66, 3, 1.6, 2),
     (POTTS, 3, 17, 3, 1.8, 5),
     (POTTS, 3, 34, 4, 1.6, 3),
+    (POTTS, 3, 20, 10, 1.2, 3),     # q = 10: the largest q with packed state counts
     (XY, 2, 5, 0, 0.89, 15),
     (XY, 2, 70, 0, 0.89, 5),
     (XY, 2, 131, 0, 1.2, 3),
