@@ -63,3 +63,75 @@ def test_random_case(i, model, dim, L, q, T, tile, start, seed):
     compare_lattice(model, lat.get_state(), lat.get_labels(), lat.get_bonds(), ref)
     compare_records(model, dim, L, q, lat.series(), ref["records"])
     lat.close()
+
+
+def draw_lattices(rng, n):
+    lats = []
+    for _ in range(n):
+        model = int(rng.integers(0, 3))
+        dim = int(rng.integers(2, 4))
+        L = int(rng.integers(3, 151)) if dim == 2 else int(rng.integers(3, 33))
+        q = 2 if model == 0 else (0 if model == 2 else int(rng.choice([2, 3, 4, 10, 11, 256])))
+        lats.append(dict(model=model, dim=dim, L=L, q=q, beta=float(rng.uniform(0.2, 1.2)),
+                         seed=int(rng.integers(1, 1 << 30)), replica=int(rng.integers(0, 8))))
+    return lats
+
+
+def oracle_run(j, n):
+    s0 = oracle.init_state(j["model"], j["dim"], j["L"], j["q"], j["seed"], j["replica"])
+    return oracle.sweeps(j["model"], j["dim"], j["L"], j["q"], j["beta"], j["seed"], j["replica"], 0, n, s0)
+
+
+@pytest.mark.parametrize("b", range(4))
+def test_random_batch(b):
+    """A batch of 16 random lattices, a random chunk length and uneven sweep
+    counts, swept in two calls."""
+    rng = np.random.default_rng(1000 + b)
+    lats = draw_lattices(rng, 16)
+    chunk = int(rng.choice([1, 3, 8, 32]))
+    c1 = rng.integers(0, 5, len(lats))
+    c2 = rng.integers(0, 4, len(lats))
+    say(f"[random batch {b}] chunk={chunk} {[(j['model'], j['dim'], j['L']) for j in lats]}")
+    bt = sw.Batch(lats)
+    bt.set_chunk(chunk)
+    bt.sweep_counts(c1)
+    bt.sweep_counts(c2)
+    for j, m, n in zip(lats, bt.members, c1 + c2):
+        assert m.sweep_index() == n
+        if n == 0:
+            continue
+        ref = oracle_run(j, int(n))
+        compare_lattice(j["model"], m.get_state(), m.get_labels(), m.get_bonds(), ref)
+        compare_records(j["model"], j["dim"], j["L"], j["q"], m.series(), ref["records"])
+    bt.close()
+
+
+@pytest.mark.parametrize("s", range(3))
+def test_random_server(s):
+    """30 random jobs through the server under a budget of a few jobs at
+    once, with a random number of active jobs and chunk length."""
+    rng = np.random.default_rng(2000 + s)
+    jobs = draw_lattices(rng, 30)
+    for j in jobs:
+        j["sweeps"] = int(rng.integers(1, 12))
+    budget = 4 * max(sw.footprint(j["model"], j["dim"], j["L"], j["q"]) for j in jobs)
+    max_active, chunk = int(rng.choice([2, 5, 16])), int(rng.choice([1, 4, 32]))
+    say(f"[random server {s}] max_active={max_active} chunk={chunk}")
+    srv = sw.Server(budget, max_active=max_active, chunk=chunk)
+    ids = [srv.submit(j["model"], j["dim"], j["L"], j["q"], j["beta"], j["seed"], j["replica"], j["sweeps"])
+           for j in jobs]
+    left, steps = len(jobs), 0
+    while left > 0:
+        left = srv.step()
+        steps += 1
+        assert steps < 2000
+    for i, j in zip(ids, jobs):
+        r = srv.poll(i, j["model"], j["L"] ** j["dim"])
+        assert r is not None and r["status"] == 0 and r["sweeps"] == j["sweeps"]
+        ref = oracle_run(j, j["sweeps"])
+        if j["model"] == 2:
+            d = np.abs(r["state"].astype(np.float64) - ref["state"])
+            assert np.minimum(d, 2 * np.pi - d).max() < 1e-5
+        else:
+            np.testing.assert_array_equal(r["state"], ref["state"])
+    srv.close()
