@@ -1,0 +1,47 @@
+"""End-to-end physics of the GPU chain, beyond trajectory parity: the Binder
+ratio B = <m^4>/<m^2>^2 of the Ising model around its critical point, the
+quantity whose finite-size scaling locates T_c in Sec. 3.  As L grows, B
+tends to 1 in the ordered phase, to 3 in the disordered phase, and to a
+universal value at T_c (about 1.168 on the square lattice, about 1.60 on the
+simple cubic one), so the curves of two sizes cross near T_c.  The seeds are
+fixed, so each run gives the same numbers; the bounds leave room for the
+finite-size corrections at these small sides."""
+import sys
+
+import pytest
+
+from paper_1403_7560_amd import inputs
+
+sw = pytest.importorskip("paper_1403_7560_amd")
+pytestmark = pytest.mark.gpu
+
+WARM, SWEEPS = 2000, 20000
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def binder(dim, L, T, seed):
+    lat = sw.Lattice(sw.ISING, dim, L, 2, 1.0 / T, seed)
+    lat.sweep(WARM)
+    lat.reset_measure()
+    lat.sweep(SWEEPS)
+    g = lat.measure()
+    lat.close()
+    return g["m4"] / g["m2"] ** 2
+
+
+@pytest.mark.parametrize("dim,Ls,tc,at_tc", [(2, (16, 32), inputs.TC_ISING_2D, (1.14, 1.20)),
+                                             (3, (8, 16), inputs.TC_ISING_3D, (1.50, 1.66))])
+def test_binder_ratio_crosses_at_tc(dim, Ls, tc, at_tc):
+    B = {}
+    for f in (0.93, 1.0, 1.07):
+        for L in Ls:
+            B[f, L] = binder(dim, L, f * tc, seed=7 + L)
+            say(f"[binder] {dim}D L={L} T={f:.2f} Tc: B={B[f, L]:.4f}")
+    small, large = Ls
+    assert B[0.93, large] < B[0.93, small] < B[1.07, small] < B[1.07, large]
+    for L in Ls:
+        assert at_tc[0] < B[1.0, L] < at_tc[1]
