@@ -1,9 +1,11 @@
 """End-to-end physics of the GPU chain, beyond trajectory parity: the Binder
-ratio B = <m^4>/<m^2>^2 of the Ising model around its critical point, the
-quantity whose finite-size scaling locates T_c in Sec. 3.  As L grows, B
-tends to 1 in the ordered phase, to 3 in the disordered phase, and to a
-universal value at T_c (about 1.168 on the square lattice, about 1.60 on the
-simple cubic one), so the curves of two sizes cross near T_c.  The seeds are
+ratio B = <m^4>/<m^2>^2 around the critical point, the quantity whose
+finite-size scaling locates T_c in Sec. 3.  As L grows, B tends to 1 in the
+ordered phase, to its Gaussian value in the disordered phase (3 for the
+one-component Ising magnetisation, 2 for the two-component XY one), and to a
+universal value at T_c (Ising: about 1.168 on the square lattice, about 1.60
+on the simple cubic one; 3D XY: about 1.243), so the curves of two sizes
+cross near T_c.  The seeds are
 fixed, so each run gives the same numbers; the bounds leave room for the
 finite-size corrections at these small sides."""
 import sys
@@ -23,8 +25,8 @@ def say(*a):
     sys.stdout.flush()
 
 
-def binder(dim, L, T, seed):
-    lat = sw.Lattice(sw.ISING, dim, L, 2, 1.0 / T, seed)
+def binder(model, dim, L, T, seed):
+    lat = sw.Lattice(model, dim, L, 2 if model == sw.ISING else 0, 1.0 / T, seed)
     lat.sweep(WARM)
     lat.reset_measure()
     lat.sweep(SWEEPS)
@@ -33,14 +35,15 @@ def binder(dim, L, T, seed):
     return g["m4"] / g["m2"] ** 2
 
 
-@pytest.mark.parametrize("dim,Ls,tc,at_tc", [(2, (16, 32), inputs.TC_ISING_2D, (1.14, 1.20)),
-                                             (3, (8, 16), inputs.TC_ISING_3D, (1.50, 1.66))])
-def test_binder_ratio_crosses_at_tc(dim, Ls, tc, at_tc):
+@pytest.mark.parametrize("model,dim,Ls,tc,at_tc", [(0, 2, (16, 32), inputs.TC_ISING_2D, (1.14, 1.20)),
+                                                   (0, 3, (8, 16), inputs.TC_ISING_3D, (1.50, 1.66)),
+                                                   (2, 3, (8, 16), inputs.TC_XY_3D, (1.20, 1.28))])
+def test_binder_ratio_crosses_at_tc(model, dim, Ls, tc, at_tc):
     B = {}
     for f in (0.93, 1.0, 1.07):
         for L in Ls:
-            B[f, L] = binder(dim, L, f * tc, seed=7 + L)
-            say(f"[binder] {dim}D L={L} T={f:.2f} Tc: B={B[f, L]:.4f}")
+            B[f, L] = binder(model, dim, L, f * tc, seed=7 + L)
+            say(f"[binder] model={model} {dim}D L={L} T={f:.2f} Tc: B={B[f, L]:.4f}")
     small, large = Ls
     assert B[0.93, large] < B[0.93, small] < B[1.07, small] < B[1.07, large]
     for L in Ls:
