@@ -17,16 +17,29 @@
  *   site index  i = x + L*(y + L*z), x fastest; N = L^dim.
  *   bond byte   bit mu (0=x,1=y,2=z) = bond between i and its +mu neighbour.
  *   labels      int32, minimum site index of the cluster.
- *   random      Philox4x32-10; word w of stream (tag, sweep n) of replica r
- *               is lane w%4 of Philox(counter=(w/4, n, tag, r),
- *               key=(seed mod 2^32, seed div 2^32)); tags: bond 0, bond z 1,
- *               bond tie 2, cluster 3, global 4, init 5.  The sweep index n is
- *               0-based and cumulative over calls.  The 32-bit uniform of bond
- *               (i, mu) is P*2^16 + S: P = high (x) / low (y) half of word i of
- *               tag 0, or for z the high (i even) / low (i odd) half of word
- *               i/2 of tag 1; S = high half of word dim*i+mu of tag 2.  A
- *               cluster labelled g takes bit g%32 of word g/32 of tag 3
- *               (Ising, XY, Potts q=2) or word g of tag 3 (Potts q>=3).
+ *   random      Philox4x32-10 (Salmon et al., SC'11; the paper's program
+ *               notes in Sec. 2 allow any generator).  Word w of stream
+ *               (tag, sweep n) of replica r is lane w%4 of
+ *               Philox(counter=(w/4, n, tag, r), key=(seed mod 2^32,
+ *               seed div 2^32)); tags: bond 0, bond z 1, bond tie 2,
+ *               cluster 3, global 4, init 5.  The sweep index n is 0-based
+ *               and cumulative over calls.
+ *               Column blocks: for site (x, y, z) the block with counter
+ *               word b4 = x + L*(floor(y/4) + ceil(L/4)*z) holds in its lanes
+ *               0..3 the words of sites (x, 4*floor(y/4) + 0..3, z).
+ *               The 32-bit uniform of bond (i, mu), i = (x, y, z), is
+ *               P*2^16 + S.  Primary P: for x the high half, for y the low
+ *               half, of lane y%4 of the tag-0 block b4; for z the high
+ *               (y even) or low (y odd) half of lane floor((y%8)/2) of the
+ *               tag-1 block b8 = x + L*(floor(y/8) + ceil(L/8)*z).
+ *               Secondary S: high half of word dim*i+mu of tag 2 (row-major
+ *               i; it decides only when P equals the threshold's high half).
+ *               A cluster labelled g takes bit g%32 of word g/32 of tag 3
+ *               (Ising, XY, Potts q=2: bit set = flip / mirror / state 1),
+ *               or, for Potts q>=3, the state floor(w*q/2^32) from the tag-3
+ *               word w of site g in the column blocks (lane y%4 of block b4).
+ *               The hot start takes word i of tag 5 at n = 0; the XY mirror
+ *               angle phi of sweep n takes words 0 and 1 of tag 4 (53 bits).
  *   couplings   J = k_B = 1, beta = 1/T.  Bond probability: Ising
  *               1-exp(-2 beta) (Sec. 2, step (1)), Potts 1-exp(-beta), XY
  *               1-exp(-2 beta sigma_i sigma_j) on the projections
@@ -35,7 +48,11 @@
  *
  * Errors: every int-returning call returns 0 (or a count) on success and a
  * negative SW_E_* code on failure; sw_last_error() gives a message for the
- * calling thread.  Handles are not thread-safe: one thread per handle.
+ * calling thread.  Label walks and unions on the device are bounded (by
+ * N + 1 steps, which a valid label forest never needs); an iterative
+ * labeller is bounded by its iteration cap.  A call whose sweeps hit either
+ * bound returns SW_E_NOCONV and that sweep's labels and states are not
+ * trustworthy.  Handles are not thread-safe: one thread per handle.
  * All host pointers are owned by the caller and must hold the stated number
  * of elements; calls that take them are synchronous.  Device memory is owned
  * by the library and freed by sw_destroy / sw_batch_destroy.
@@ -130,6 +147,49 @@ int sw_sweep(sw_handle h, int64_t n);
  * With no records the current configuration alone is measured. */
 int sw_measure(sw_handle h, double *m2, double *m4, double *energy, sw_cluster_stats *cs);
 
+/* Moments of the recorded series since the last sw_reset_measure (the
+ * current configuration alone when nothing is recorded): the outputs of the
+ * paper's program (Sec. 2: <m^2>, <m^4>, energy and specific heat per spin),
+ * <|m|>, and the moment ratio of Sec. 3, Eq. (6).  m = M/N with M of Eq. (4)
+ * (Ising), sqrt of Eq. (5) (Potts) or |(sum cos, sum sin)| (XY). */
+typedef struct {
+    int64_t n;            /* records averaged */
+    double abs_m;         /* <|m|> */
+    double m2, m4;        /* <m^2>, <m^4> */
+    double energy;        /* <E>/N */
+    double energy2;       /* <(E/N)^2> */
+    double specific_heat; /* beta^2 (<E^2> - <E>^2) / N */
+    double binder;        /* <m^4> / <m^2>^2 (0 when <m^2> = 0) */
+} sw_moments;
+int sw_get_moments(sw_handle h, sw_moments *out);
+
+/* Global phase of step (2), the label equivalence across tiles (the bond
+ * kernel labels every tile itself).  SW_LABEL_UNION (default): one pass that
+ * links tile roots with device-scope atomicMin, reaching the fixed point
+ * directly.  The paper's two iterative labellers, chosen like its program's
+ * `algorithm` parameter (Sec. 2, program notes; label-equivalence
+ * paragraphs): SW_LABEL_HAWICK (0; scanning with atomicMin on a temporary R,
+ * analysis of R chains, labeling label <- R[label]) and SW_LABEL_KALENTEV
+ * (1; one label variable, scanning and analysis, no atomic operation), each
+ * iterated inside one launch per sweep until a scan changes nothing, at most
+ * max_iterations (1 .. 4096) scans; reaching the cap without convergence
+ * makes the call return SW_E_NOCONV.  Every labeller yields the same labels
+ * and so the same trajectory.  Plain form only: batched and served lattices
+ * use SW_LABEL_UNION.  Resets the labelling statistics. */
+enum sw_labeller { SW_LABEL_HAWICK = 0, SW_LABEL_KALENTEV = 1, SW_LABEL_UNION = 2 };
+int sw_set_labeller(sw_handle h, int algorithm, int max_iterations);
+
+/* Labelling statistics since the last sw_set_labeller: sweeps labelled by an
+ * iterative labeller, the scans they ran in total and the most any one ran
+ * (any pointer may be NULL; all zero under SW_LABEL_UNION). */
+int sw_get_label_stats(sw_handle h, int64_t *labellings, int64_t *scans, int64_t *max_scans);
+
+/* Test hook: bound every device label walk and union retry of this handle by
+ * `cap` steps (1 .. 2^32-1; default N + 1, never reached on a valid forest).
+ * A tiny cap makes the kernels stop early, flag the sweep and return
+ * SW_E_NOCONV, which is how the error path is exercised. */
+int sw_set_walk_cap(sw_handle h, int64_t cap);
+
 /* Drop the recorded series (the paper's discarded MCS). */
 int sw_reset_measure(sw_handle h);
 
@@ -168,7 +228,9 @@ int sw_set_sweep_index(sw_handle h, int64_t n);
  * [0, (float)2pi) or NaN) with SW_E_INVALID. */
 int sw_get_state(sw_handle h, void *host_state);
 int sw_set_state(sw_handle h, const void *host_state);
-/* Minimum-index labels (N int32) and bond bytes (N uint8) of the last sweep. */
+/* Minimum-index labels (N int32) and bond bytes (N uint8) of the last sweep
+ * run (whatever sw_set_sweep_index or sw_set_state did since); identity
+ * labels and zero bonds before any sweep. */
 int sw_get_labels(sw_handle h, int32_t *host_labels);
 int sw_get_bonds(sw_handle h, uint8_t *host_bonds);
 /* Lattice parameters of a handle (any pointer may be NULL). */

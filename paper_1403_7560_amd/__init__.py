@@ -13,6 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libswmc.so")
 
 ISING, POTTS, XY = 0, 1, 2
+LABEL_HAWICK, LABEL_KALENTEV, LABEL_UNION = 0, 1, 2
 STATE_DTYPE = {ISING: np.int8, POTTS: np.uint8, XY: np.float32}
 ERRORS = {-1: "SW_E_INVALID", -2: "SW_E_NOMEM", -3: "SW_E_DEVICE", -4: "SW_E_NOCONV",
           -5: "SW_E_BUSY", -6: "SW_E_NOTFOUND"}
@@ -27,6 +28,12 @@ class SWError(RuntimeError):
 class ClusterStats(ctypes.Structure):
     _fields_ = [("n_clusters", ctypes.c_int64), ("max_cluster", ctypes.c_int64),
                 ("sum_c2", ctypes.c_int64)]
+
+
+class Moments(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("abs_m", ctypes.c_double), ("m2", ctypes.c_double),
+                ("m4", ctypes.c_double), ("energy", ctypes.c_double), ("energy2", ctypes.c_double),
+                ("specific_heat", ctypes.c_double), ("binder", ctypes.c_double)]
 
 
 class Record(ctypes.Structure):
@@ -65,6 +72,10 @@ SIGNATURES = {
     "sw_sweep": (i32, [vp, i64]),
     "sw_measure": (i32, [vp, vp, vp, vp, vp]),
     "sw_reset_measure": (i32, [vp]),
+    "sw_get_moments": (i32, [vp, vp]),
+    "sw_set_walk_cap": (i32, [vp, i64]),
+    "sw_set_labeller": (i32, [vp, i32, i32]),
+    "sw_get_label_stats": (i32, [vp, vp, vp, vp]),
     "sw_series": (i64, [vp, vp, i64]),
     "sw_set_measure": (i32, [vp, i32]),
     "sw_destroy": (None, [vp]),
@@ -175,6 +186,25 @@ class Lattice:
                                 ctypes.byref(cs)))
         return {"m2": m2.value, "m4": m4.value, "energy": e.value,
                 "n_clusters": cs.n_clusters, "max_cluster": cs.max_cluster, "sum_c2": cs.sum_c2}
+
+    def moments(self):
+        """<|m|>, <m^2>, <m^4>, <E>/N, <(E/N)^2>, specific heat per spin and
+        the moment ratio over the recorded series (sw_get_moments)."""
+        m = Moments()
+        _check(lib().sw_get_moments(self.h, ctypes.byref(m)))
+        return {f: getattr(m, f) for f, _ in Moments._fields_}
+
+    def set_labeller(self, algorithm, max_iterations=64):
+        """0 Hawick, 1 Kalentev (the paper's iterative labellers), 2 one-pass union."""
+        _check(lib().sw_set_labeller(self.h, int(algorithm), int(max_iterations)))
+
+    def label_stats(self):
+        v = np.zeros(3, dtype=np.int64)
+        _check(lib().sw_get_label_stats(self.h, _ptr(v[0:]), _ptr(v[1:]), _ptr(v[2:])))
+        return {"labellings": int(v[0]), "scans": int(v[1]), "max_scans": int(v[2])}
+
+    def set_walk_cap(self, cap):
+        _check(lib().sw_set_walk_cap(self.h, int(cap)))
 
     def reset_measure(self):
         _check(lib().sw_reset_measure(self.h))

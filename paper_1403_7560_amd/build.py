@@ -30,22 +30,39 @@ def hipcc():
 
 
 def build(verbose=False):
+    """Compile every kernel translation unit (in parallel) and the host
+    runtime, then link them into libswmc.so."""
     os.makedirs(BUILD, exist_ok=True)
     cc = hipcc()
-    kobj = os.path.join(BUILD, "sw_kernels.o")
+    hips = sorted(f for f in os.listdir(CSRC) if f.endswith(".hip"))
+    objs, compiles = [], []
+    for f in hips:
+        o = os.path.join(BUILD, f[:-4] + ".o")
+        objs.append(o)
+        compiles.append([cc, "-c", os.path.join(CSRC, f), "-o", o] + DEVICE_FLAGS)
     eobj = os.path.join(BUILD, "sw_engine.o")
-    steps = [
-        [cc, "-c", os.path.join(CSRC, "sw_kernels.hip"), "-o", kobj] + DEVICE_FLAGS,
-        [cc, "-c", os.path.join(CSRC, "sw_engine.cpp"), "-o", eobj] + HOST_FLAGS,
-        [cc, "-shared", f"--offload-arch={ARCH}", "-fPIC", kobj, eobj, "-o", LIB + ".tmp"],
-    ]
-    for cmd in steps:
+    objs.append(eobj)
+    compiles.append([cc, "-c", os.path.join(CSRC, "sw_engine.cpp"), "-o", eobj] + HOST_FLAGS)
+    procs = []
+    for cmd in compiles:
         if verbose:
             print(" ".join(cmd), flush=True)
-        r = subprocess.run(cmd, capture_output=True, text=True)
-        if r.returncode != 0:
-            sys.stderr.write(r.stdout + r.stderr)
-            raise RuntimeError(f"build step failed: {' '.join(cmd[:3])}")
+        procs.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))
+    failed = None
+    for cmd, p in procs:
+        out, _ = p.communicate()
+        if p.returncode != 0:
+            sys.stderr.write(out)
+            failed = failed or cmd
+    if failed:
+        raise RuntimeError(f"build step failed: {' '.join(failed[:3])}")
+    link = [cc, "-shared", f"--offload-arch={ARCH}", "-fPIC"] + objs + ["-o", LIB + ".tmp"]
+    if verbose:
+        print(" ".join(link), flush=True)
+    r = subprocess.run(link, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("link step failed")
     os.replace(LIB + ".tmp", LIB)
     return LIB
 

@@ -70,6 +70,21 @@ int validate(int model, int dim, int L, int q, double beta)
     return SW_OK;
 }
 
+// Reads and clears a device error word (ERR_* bits) once the work that may
+// set it has completed; SW_E_NOCONV when a bit was set.
+int check_error_word(uint32_t *err)
+{
+    uint32_t e = 0;
+    HIPCHK(hipMemcpy(&e, err, 4, hipMemcpyDeviceToHost));
+    if (e == 0) return SW_OK;
+    const uint32_t zero = 0;
+    HIPCHK(hipMemcpy(err, &zero, 4, hipMemcpyHostToDevice));
+    std::string what;
+    if (e & ERR_WALK) what += "a label walk or union exceeded its step cap";
+    if (e & ERR_ITER) what += std::string(what.empty() ? "" : "; ") + "iterative labelling hit its iteration cap";
+    return fail(SW_E_NOCONV, "labelling did not reach its fixed point: " + what);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -97,7 +112,21 @@ struct Lattice {
     int64_t rec_cap = 0;
     bool measure = true;
     bool store_bonds = true;
-    bool swept = false;
+    // index of the last sweep whose labels are in the label buffers (-1: none);
+    // the buffer is picked by its parity, whatever the sweep index is now
+    int64_t labelled = -1;
+    uint32_t walk_cap = 0;  // bound of every label walk (set to N + 1 at creation)
+    uint32_t *err = nullptr;  // device error word (ERR_* bits); labelling statistics at byte 64
+    // global phase of the labelling: SW_LABEL_UNION (one atomic pass), or the
+    // paper's iterative SW_LABEL_HAWICK / SW_LABEL_KALENTEV (plain form)
+    int labeller = SW_LABEL_UNION;
+    int max_iters = 0;
+    int edge_cap = 0;              // unique face pairs a tile can hold
+    uint64_t *edges = nullptr;     // [ntiles][edge_cap]
+    int32_t *ecount = nullptr;     // [ntiles]
+    uint32_t *rbuf = nullptr;      // Hawick's R, N words
+    uint32_t *ctl = nullptr;       // barrier and convergence words of one launch
+    int ctl_words = 0;
     void *state = nullptr;
     uint32_t *label = nullptr;   // label words of even sweeps
     uint32_t *label2 = nullptr;  // label words of odd sweeps
@@ -138,7 +167,8 @@ struct Lattice {
 
     void release()
     {
-        void *ptrs[] = {state, label, label2, theta_w[0], theta_w[1], bond, face, part, rec, d_solo, d_tmap};
+        void *ptrs[] = {state, label, label2, theta_w[0], theta_w[1], bond, face, part, rec, d_solo, d_tmap, err,
+                        edges, ecount, rbuf, ctl};
         for (void *p : ptrs)
             if (p) (void)hipFree(p);
         state = nullptr;
@@ -151,6 +181,11 @@ struct Lattice {
         rec = nullptr;
         d_solo = nullptr;
         d_tmap = nullptr;
+        err = nullptr;
+        edges = nullptr;
+        ecount = nullptr;
+        rbuf = nullptr;
+        ctl = nullptr;
     }
 
     static int64_t footprint(int model, int dim, int L, int q, int variant)
@@ -211,8 +246,70 @@ struct Lattice {
         }
         d.part = part;
         d.rec = rec;
+        d.err = err;
+        d.walk_cap = walk_cap;
+        d.edges = edges;
+        d.ecount = ecount;
+        d.edge_cap = edge_cap;
+        d.rbuf = rbuf;
+        d.lstats = (uint64_t *)((char *)err + 64);
         return d;
     }
+
+    // Select the global labelling phase; the iterative ones get their edge
+    // lists, Hawick's R and the launch control words here.
+    int set_labeller(int alg, int cap)
+    {
+        if (alg != SW_LABEL_HAWICK && alg != SW_LABEL_KALENTEV && alg != SW_LABEL_UNION)
+            return fail(SW_E_INVALID, "algorithm must be 0 (Hawick), 1 (Kalentev) or 2 (union)");
+        if (cap < 1 || cap > 4096) return fail(SW_E_INVALID, "iteration cap must be in [1, 4096]");
+        if (alg != SW_LABEL_UNION) {
+            int ec = 0;
+            const int ext[3] = {ts.tx, ts.ty, dim == 3 ? ts.tz : 1};
+            const int64_t T = (int64_t)ext[0] * ext[1] * ext[2];
+            for (int mu = 0; mu < dim; ++mu)
+                if (tiles[mu] > 1) ec += (int)(T / ext[mu]);
+            if (!edges && hipMalloc(&edges, (size_t)ntiles * std::max(ec, 1) * 8) != hipSuccess)
+                return fail(SW_E_NOMEM, "edge list allocation failed");
+            if (!ecount && hipMalloc(&ecount, (size_t)ntiles * 4) != hipSuccess)
+                return fail(SW_E_NOMEM, "edge count allocation failed");
+            if (alg == SW_LABEL_HAWICK && !rbuf && hipMalloc(&rbuf, (size_t)N * 4) != hipSuccess)
+                return fail(SW_E_NOMEM, "R allocation failed");
+            const int words = label_ctl_words(cap);
+            if (words > ctl_words) {
+                if (ctl) HIPCHK(hipFree(ctl));
+                ctl = nullptr;
+                if (hipMalloc(&ctl, (size_t)words * 4) != hipSuccess) return fail(SW_E_NOMEM, "control words allocation failed");
+                ctl_words = words;
+            }
+            edge_cap = ec;
+        }
+        labeller = alg;
+        max_iters = cap;
+        const uint64_t zero[3] = {0, 0, 0};
+        HIPCHK(hipMemcpy((char *)err + 64, zero, sizeof(zero), hipMemcpyHostToDevice));
+        return SW_OK;
+    }
+
+    // Global phase of sweep k of the current chain.
+    hipError_t launch_global(uint32_t k)
+    {
+        if (ntiles <= 1) return hipSuccess;  // one tile: no faces, the bond kernel wrote the record
+        if (labeller == SW_LABEL_UNION) return launch_merge(dim, model, variant, d_solo, d_tmap, ntiles, k, stream);
+        return launch_label_iter(dim, model, variant, labeller, d_solo, d_tmap, ntiles, k, ctl, max_iters, stream);
+    }
+
+    // Descriptor whose previous sweep is the last labelled one (the label
+    // readers take the buffer of sweep0 - 1).
+    InstDesc labelled_desc() const
+    {
+        InstDesc d = desc();
+        d.sweep0 = (uint32_t)(labelled + 1);
+        return d;
+    }
+
+    // Reads and clears the device error word after a synchronised chain.
+    int check_errors() { return check_error_word(err); }
 
     int grow_records(int64_t need)
     {
@@ -268,12 +365,16 @@ struct Lattice {
             hipMalloc(&face, (size_t)std::max<int64_t>(face_total, 1) * 4) != hipSuccess ||
             hipMalloc(&part, (size_t)ntiles * nslots * 8) != hipSuccess ||
             hipMalloc(&d_solo, sizeof(InstDesc)) != hipSuccess ||
-            hipMalloc(&d_tmap, (size_t)ntiles * sizeof(int2)) != hipSuccess) {
+            hipMalloc(&d_tmap, (size_t)ntiles * sizeof(int2)) != hipSuccess ||
+            hipMalloc(&err, 256) != hipSuccess) {
             (void)hipGetLastError();
             return fail(SW_E_NOMEM, "device allocation failed");
         }
+        walk_cap = (uint32_t)(N + 1);
+        max_iters = 64;
         rc = grow_records(1024);
         if (rc) return rc;
+        HIPCHK(hipMemsetAsync(err, 0, 256, stream));
         std::vector<int2> tm, cut;
         append_tiles(*this, 0, tm, cut);
         nfull = (int)tm.size();
@@ -321,8 +422,7 @@ struct Lattice {
                 if (ev) HIPCHK(hipEventRecord(ev[0], stream));
                 HIPCHK(launch_bond(model, dim, variant, d_solo, d_tmap, ntiles, nfull, (uint32_t)k, 0, stream));
                 if (ev) HIPCHK(hipEventRecord(ev[1], stream));
-                // one tile: no faces, and the bond kernel writes the record
-                if (ntiles > 1) HIPCHK(launch_merge(dim, model, variant, d_solo, d_tmap, ntiles, (uint32_t)k, stream));
+                HIPCHK(launch_global((uint32_t)k));
                 if (ev && profiling > 1) HIPCHK(hipEventRecord(ev[2], stream));
             }
             HIPCHK(launch_flip(model, dim, variant, d_solo, d_tmap, ntiles, FLIP_LAST, stream));
@@ -340,8 +440,10 @@ struct Lattice {
             }
             sweep += m;
             if (measure) rec_count += m;
-            swept = true;
+            if (m > 0) labelled = sweep - 1;
             n -= m;
+            int rc = check_errors();
+            if (rc) return rc;
         }
         return SW_OK;
     }
@@ -408,7 +510,7 @@ struct Lattice {
     int cluster_stats(sw_cluster_stats *cs)
     {
         std::memset(cs, 0, sizeof(*cs));
-        if (!swept) return SW_OK;
+        if (labelled < 0) return SW_OK;
         int32_t *scratch = nullptr;
         unsigned long long *out = nullptr;
         if (hipMalloc(&scratch, (size_t)N * 4) != hipSuccess || hipMalloc(&out, 24) != hipSuccess) {
@@ -416,8 +518,8 @@ struct Lattice {
             return fail(SW_E_NOMEM, "cluster statistics scratch allocation failed");
         }
         unsigned long long h[3] = {0, 0, 0};
-        // a current descriptor: its sweep index names the last sweep's label buffer
-        InstDesc d = desc();
+        // its sweep index names the last labelled sweep's buffer
+        InstDesc d = labelled_desc();
         hipError_t e = hipMemcpyAsync(d_solo, &d, sizeof(d), hipMemcpyHostToDevice, stream);
         if (e == hipSuccess) e = hipMemcpyAsync(out, h, 24, hipMemcpyHostToDevice, stream);
         if (e == hipSuccess) e = launch_cluster_stats(d_solo, 0, N, scratch, out, stream);
@@ -429,10 +531,14 @@ struct Lattice {
         cs->n_clusters = (int64_t)h[0];
         cs->max_cluster = (int64_t)h[1];
         cs->sum_c2 = (int64_t)h[2];
-        return SW_OK;
+        return check_errors();
     }
 
-    int averages(double *m2, double *m4, double *energy)
+    // Moments of the recorded series since the last reset (the current
+    // configuration alone when nothing is recorded): Sec. 2's printed
+    // outputs (<m^2>, <m^4>, energy and specific heat per spin) plus <|m|>
+    // and the moment ratio of Sec. 3, Eq. (6).
+    int moments(sw_moments *o)
     {
         std::vector<sw_record> recs;
         if (rec_count > 0) {
@@ -444,18 +550,43 @@ struct Lattice {
             if (rc) return rc;
             recs.push_back(to_record(row.data(), sweep));
         }
-        double a2 = 0, a4 = 0, ae = 0;
-        const double n2 = (double)N * (double)N;
+        const double n = (double)recs.size(), dN = (double)N, n2 = dN * dN;
+        double a1 = 0, a2 = 0, a4 = 0, ae = 0;
         for (const sw_record &r : recs) {
             const double x = r.mag2 / n2;
+            a1 += std::fabs(r.mag) / dN;
             a2 += x;
             a4 += x * x;
-            ae += r.energy / (double)N;
+            ae += r.energy / dN;
         }
-        const double c = (double)recs.size();
-        if (m2) *m2 = a2 / c;
-        if (m4) *m4 = a4 / c;
-        if (energy) *energy = ae / c;
+        const double em = ae / n;
+        double ve = 0, ae2 = 0;  // two passes: the variance without cancellation
+        for (const sw_record &r : recs) {
+            const double e = r.energy / dN;
+            ve += (e - em) * (e - em);
+            ae2 += e * e;
+        }
+        std::memset(o, 0, sizeof(*o));
+        o->n = (int64_t)recs.size();
+        o->abs_m = a1 / n;
+        o->m2 = a2 / n;
+        o->m4 = a4 / n;
+        o->energy = em;
+        o->energy2 = ae2 / n;
+        // C/N = beta^2 (<E^2> - <E>^2) / N = beta^2 N (<e^2> - <e>^2), e = E/N
+        o->specific_heat = beta * beta * dN * (ve / n);
+        o->binder = o->m2 > 0.0 ? o->m4 / (o->m2 * o->m2) : 0.0;
+        return SW_OK;
+    }
+
+    int averages(double *m2, double *m4, double *energy)
+    {
+        sw_moments o;
+        int rc = moments(&o);
+        if (rc) return rc;
+        if (m2) *m2 = o.m2;
+        if (m4) *m4 = o.m4;
+        if (energy) *energy = o.energy;
         return SW_OK;
     }
 };
@@ -538,6 +669,7 @@ struct sw_batch_s {
     std::vector<Group> groups;
     InstDesc *d_desc = nullptr;
     InstDesc *h_desc = nullptr;  // pinned
+    uint32_t *d_err = nullptr;   // error word shared by the members' batched launches
     hipStream_t stream = nullptr;
     int chunk = 16;
     hipGraphExec_t graph = nullptr;
@@ -550,6 +682,7 @@ struct sw_batch_s {
             if (g.d_tmap) (void)hipFree(g.d_tmap);
         if (d_desc) (void)hipFree(d_desc);
         if (h_desc) (void)hipHostFree(h_desc);
+        if (d_err) (void)hipFree(d_err);
         lats.clear();
         if (stream) (void)hipStreamDestroy(stream);
     }
@@ -579,8 +712,10 @@ struct sw_batch_s {
             HIPCHK(hipMemcpy(g.d_tmap, tm.data(), tm.size() * sizeof(int2), hipMemcpyHostToDevice));
         }
         if (hipMalloc(&d_desc, lats.size() * sizeof(InstDesc)) != hipSuccess ||
-            hipHostMalloc(&h_desc, lats.size() * sizeof(InstDesc), hipHostMallocDefault) != hipSuccess)
+            hipHostMalloc(&h_desc, lats.size() * sizeof(InstDesc), hipHostMallocDefault) != hipSuccess ||
+            hipMalloc(&d_err, 256) != hipSuccess)
             return fail(SW_E_NOMEM, "descriptor allocation failed");
+        HIPCHK(hipMemset(d_err, 0, 256));
         return SW_OK;
     }
 
@@ -642,6 +777,7 @@ struct sw_batch_s {
             d.remaining = (uint32_t)counts[j];
             d.chunk = (uint32_t)S;
             d.count = (uint32_t)std::min<int64_t>(S, counts[j]);
+            d.err = d_err;
             h_desc[j] = d;
         }
         HIPCHK(hipMemcpyAsync(d_desc, h_desc, lats.size() * sizeof(InstDesc), hipMemcpyHostToDevice, stream));
@@ -655,9 +791,9 @@ struct sw_batch_s {
             if (counts[j] == 0) continue;
             l.sweep += counts[j];
             if (l.measure) l.rec_count += counts[j];
-            l.swept = true;
+            l.labelled = l.sweep - 1;
         }
-        return SW_OK;
+        return check_error_word(d_err);
     }
 };
 
@@ -671,6 +807,7 @@ struct ServerJob {
     double submit_s = 0, start_s = 0, finish_s = 0;
     std::unique_ptr<Lattice> lat;
     int64_t done = 0;
+    int status = 0;  // SW_E_NOCONV once a tick it took part in was flagged
 };
 
 struct sw_server_s {
@@ -687,6 +824,7 @@ struct sw_server_s {
     std::vector<Group> groups;
     InstDesc *d_desc = nullptr;
     InstDesc *h_desc = nullptr;
+    uint32_t *d_err = nullptr;  // error word shared by every tick's launches
     int desc_cap = 0;
     bool dirty = true;
 
@@ -696,6 +834,7 @@ struct sw_server_s {
             if (g.d_tmap) (void)hipFree(g.d_tmap);
         if (d_desc) (void)hipFree(d_desc);
         if (h_desc) (void)hipHostFree(h_desc);
+        if (d_err) (void)hipFree(d_err);
         active.clear();
         queue.clear();
         if (stream) (void)hipStreamDestroy(stream);
@@ -754,7 +893,7 @@ struct sw_server_s {
             r.start_s = sj.start_s;
             r.finish_s = t;
             int rc = sj.lat->averages(&r.m2, &r.m4, &r.energy);
-            r.status = rc;
+            r.status = sj.status ? sj.status : rc;
             std::vector<uint8_t> st((size_t)sj.lat->N * state_bytes(sj.lat->model));
             if (hipMemcpy(st.data(), sj.lat->state, st.size(), hipMemcpyDeviceToHost) != hipSuccess)
                 r.status = SW_E_DEVICE;
@@ -788,9 +927,6 @@ struct sw_server_s {
             }
             sj->start_s = t;
             used += sj->footprint;
-            if (sj->job.sweeps == 0) {
-                sj->lat->swept = false;
-            }
             active.push_back(std::move(sj));
             dirty = true;
         }
@@ -818,6 +954,7 @@ struct sw_server_s {
                 d.remaining = (uint32_t)c;
                 d.chunk = (uint32_t)chunk;
                 d.count = (uint32_t)c;
+                d.err = d_err;
                 h_desc[j] = d;
                 maxc = std::max(maxc, c);
             }
@@ -831,13 +968,16 @@ struct sw_server_s {
             for (const Group &g : groups)
                 HIPCHK(launch_flip(g.model, g.dim, g.variant, d_desc, g.d_tmap, g.ntiles, FLIP_LAST, stream));
             HIPCHK(hipStreamSynchronize(stream));
+            // a flagged tick marks every job that took part in it
+            const bool flagged = check_error_word(d_err) != SW_OK;
             for (size_t j = 0; j < active.size(); ++j) {
                 ServerJob &sj = *active[j];
                 const int64_t c = std::min<int64_t>(chunk, sj.job.sweeps - sj.done);
                 sj.done += c;
                 sj.lat->sweep += c;
                 sj.lat->rec_count += c;
-                if (c > 0) sj.lat->swept = true;
+                if (c > 0) sj.lat->labelled = sj.lat->sweep - 1;
+                if (c > 0 && flagged) sj.status = SW_E_NOCONV;
             }
             rc = retire(now_s());
             if (rc) return rc;
@@ -994,6 +1134,38 @@ int sw_measure(sw_handle h, double *m2, double *m4, double *energy, sw_cluster_s
     return SW_OK;
 }
 
+int sw_get_moments(sw_handle h, sw_moments *out)
+{
+    CHECK_H(h);
+    if (!out) return fail(SW_E_INVALID, "NULL output");
+    return h->lat->moments(out);
+}
+
+int sw_set_labeller(sw_handle h, int algorithm, int max_iterations)
+{
+    CHECK_H(h);
+    return h->lat->set_labeller(algorithm, max_iterations);
+}
+
+int sw_get_label_stats(sw_handle h, int64_t *labellings, int64_t *scans, int64_t *max_scans)
+{
+    CHECK_H(h);
+    uint64_t v[3];
+    HIPCHK(hipMemcpy(v, (char *)h->lat->err + 64, sizeof(v), hipMemcpyDeviceToHost));
+    if (labellings) *labellings = (int64_t)v[0];
+    if (scans) *scans = (int64_t)v[1];
+    if (max_scans) *max_scans = (int64_t)v[2];
+    return SW_OK;
+}
+
+int sw_set_walk_cap(sw_handle h, int64_t cap)
+{
+    CHECK_H(h);
+    if (cap < 1 || cap > 0xFFFFFFFFll) return fail(SW_E_INVALID, "walk cap must be in [1, 2^32 - 1]");
+    h->lat->walk_cap = (uint32_t)cap;
+    return SW_OK;
+}
+
 int sw_reset_measure(sw_handle h)
 {
     CHECK_H(h);
@@ -1095,13 +1267,13 @@ int sw_get_labels(sw_handle h, int32_t *host)
     CHECK_H(h);
     if (!host) return fail(SW_E_INVALID, "NULL buffer");
     Lattice &l = *h->lat;
-    if (!l.swept) {
+    if (l.labelled < 0) {
         for (int64_t i = 0; i < l.N; ++i) host[i] = (int32_t)i;
         return SW_OK;
     }
     int32_t *tmp = nullptr;
     if (hipMalloc(&tmp, (size_t)l.N * 4) != hipSuccess) return fail(SW_E_NOMEM, "label scratch allocation failed");
-    InstDesc d = l.desc();
+    InstDesc d = l.labelled_desc();
     hipError_t e = hipMemcpyAsync(l.d_solo, &d, sizeof(d), hipMemcpyHostToDevice, l.stream);
     if (e == hipSuccess) e = hipStreamSynchronize(l.stream);
     if (e == hipSuccess) e = launch_canon(l.d_solo, 0, l.N, tmp, l.stream);
@@ -1109,7 +1281,7 @@ int sw_get_labels(sw_handle h, int32_t *host)
     if (e == hipSuccess) e = hipStreamSynchronize(l.stream);
     (void)hipFree(tmp);
     if (e != hipSuccess) return fail(SW_E_DEVICE, std::string("labels: ") + hipGetErrorString(e));
-    return SW_OK;
+    return l.check_errors();
 }
 
 int sw_get_bonds(sw_handle h, uint8_t *host)
@@ -1218,6 +1390,10 @@ sw_server sw_server_create(int64_t budget, int max_active, int chunk)
     s->stream = make_stream();
     if (!s->stream) {
         fail(SW_E_DEVICE, "hipStreamCreate failed (no HIP device?)");
+        return nullptr;
+    }
+    if (hipMalloc(&s->d_err, 256) != hipSuccess || hipMemset(s->d_err, 0, 256) != hipSuccess) {
+        fail(SW_E_NOMEM, "server error word allocation failed");
         return nullptr;
     }
     return s.release();

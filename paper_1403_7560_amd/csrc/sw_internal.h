@@ -49,7 +49,25 @@ struct InstDesc {
     int32_t face_len[3];
     int64_t *part;        // [ntiles][nslots] per-tile partial sums
     int64_t *rec;         // [rec_cap + 1][nslots]
+    // Bounded walks: a label chain or union retry longer than walk_cap steps
+    // (never reached on a valid forest, whose chains strictly decrease and so
+    // end within N steps) stops, sets ERR_WALK in *err and the host call
+    // reports SW_E_NOCONV.
+    uint32_t *err;
+    uint32_t walk_cap;
+    // Iterative labellers (Hawick 0 / Kalentev 1): per tile up to edge_cap
+    // unique (out root, in root) pairs and their count; Hawick's temporary
+    // label R (N words); labelling statistics {labellings, scans, max scans}.
+    uint64_t *edges;
+    int32_t *ecount;
+    int32_t edge_cap;
+    uint32_t *rbuf;
+    uint64_t *lstats;
 };
+
+// Bits of a lattice's device error word.
+constexpr uint32_t ERR_WALK = 1u;   // a label walk or union hit walk_cap
+constexpr uint32_t ERR_ITER = 2u;   // iterative labelling hit its iteration cap
 
 // Tile shape of a kernel variant.
 struct TileShape {
@@ -77,6 +95,25 @@ hipError_t launch_flip(int model, int dim, int variant, const InstDesc *d_desc,
 hipError_t launch_canon(const InstDesc *d_desc, int inst, int64_t N, int32_t *d_out,
                         hipStream_t s);
 hipError_t launch_advance(InstDesc *d_desc, int ninst, hipStream_t s);
+// Per-model instantiations behind launch_bond / launch_flip (one translation
+// unit each).
+hipError_t launch_bond_ising(int dim, int v, const InstDesc *dd, const int2 *tm, int nt, int nf, uint32_t k,
+                             int mode, hipStream_t s);
+hipError_t launch_bond_potts(int dim, int v, const InstDesc *dd, const int2 *tm, int nt, int nf, uint32_t k,
+                             int mode, hipStream_t s);
+hipError_t launch_bond_xy(int dim, int v, const InstDesc *dd, const int2 *tm, int nt, int nf, uint32_t k,
+                          int mode, hipStream_t s);
+hipError_t launch_flip_ising(int dim, int v, const InstDesc *dd, const int2 *tm, int nt, uint32_t k, hipStream_t s);
+hipError_t launch_flip_potts(int dim, int v, const InstDesc *dd, const int2 *tm, int nt, uint32_t k, hipStream_t s);
+hipError_t launch_flip_xy(int dim, int v, const InstDesc *dd, const int2 *tm, int nt, uint32_t k, hipStream_t s);
+
+// The paper's iterative labellers for the global phase (alg 0 Hawick, 1
+// Kalentev; defined in sw_label.hip): one cooperative launch per sweep that
+// iterates until a scan changes nothing or `cap` scans ran.  `ctl` must hold
+// label_ctl_words(cap) words; it is cleared by the launch itself.
+hipError_t launch_label_iter(int dim, int model, int variant, int alg, const InstDesc *d_desc, const int2 *d_tmap,
+                             int ntiles, uint32_t k, uint32_t *ctl, int cap, hipStream_t s);
+int label_ctl_words(int cap);
 
 }  // namespace swmc
 

@@ -104,3 +104,46 @@ def test_batched_form_full_size_ordered():
         compare_lattice(j["model"], m.get_state(), m.get_labels(), m.get_bonds(), ref)
         compare_records(j["model"], j["dim"], j["L"], j["q"], m.series(), ref["records"])
     b.close()
+
+
+WARM = 200  # GPU sweeps from the hot start before a resumed window
+
+
+@pytest.mark.parametrize("name", ["C2-potts", "C2-ising", "C3"])
+def test_plain_form_window_from_gpu_state(name):
+    """200 GPU sweeps from the hot start, then a window of two more: the
+    oracle resumes from the state the GPU evolved (at sweep index 200) and
+    must reach the same bonds, labels, states and records."""
+    (j,), _ = inputs.workload(name)
+    say(f"[full-resumed] {name}: {WARM} GPU sweeps, then {SWEEPS} compared")
+    lat = sw.Lattice(j["model"], j["dim"], j["L"], j["q"], j["beta"], j["seed"], j["replica"])
+    lat.sweep(WARM)
+    st = lat.get_state()
+    lat.reset_measure()
+    lat.sweep(SWEEPS)
+    ref = oracle.sweeps(j["model"], j["dim"], j["L"], j["q"], j["beta"], j["seed"], j["replica"], WARM, SWEEPS, st)
+    compare_lattice(j["model"], lat.get_state(), lat.get_labels(), lat.get_bonds(), ref)
+    compare_records(j["model"], j["dim"], j["L"], j["q"], lat.series(), ref["records"])
+    lat.close()
+
+
+def test_batched_form_window_from_gpu_state():
+    """The 32 C4 replicas sweep 200 times in one batch; replicas 0 and 31
+    (the ends of the temperature grid) are compared over two more sweeps
+    that the oracle resumes from their GPU-evolved states."""
+    lats, _ = inputs.workload("C4")
+    say(f"[full-resumed] C4: {WARM} batched sweeps of 32 replicas, then {SWEEPS} compared")
+    b = sw.Batch(lats)
+    b.sweep(WARM)
+    states = {r: b.members[r].get_state() for r in (0, len(lats) - 1)}
+    for m in b.members:
+        m.reset_measure()
+    b.sweep(SWEEPS)
+    for r, st in states.items():
+        j, m = lats[r], b.members[r]
+        say(f"[full-resumed] C4 replica {r} T={1.0 / j['beta']:.5f}")
+        ref = oracle.sweeps(j["model"], j["dim"], j["L"], j["q"], j["beta"], j["seed"], j["replica"], WARM,
+                            SWEEPS, st)
+        compare_lattice(j["model"], m.get_state(), m.get_labels(), m.get_bonds(), ref)
+        compare_records(j["model"], j["dim"], j["L"], j["q"], m.series(), ref["records"])
+    b.close()

@@ -72,6 +72,9 @@ CASES = [
     (POTTS, 2, 40, 256, 0.3, 4),
     (POTTS, 2, 50, 2, 1.7, 5),      # q = 2: one-bit decisions, state counts packed
     (POTTS, 2, 45, 11, 0.7, 4),     # q = 11: the smallest q counted with LDS atomics
+    (POTTS, 2, 70, 65, 0.5, 4),     # q > 64: state counts read from two wavefronts' queue memory
+    (POTTS, 2, 130, 129, 0.45, 3),  # q > 128: and from three
+    (POTTS, 3, 20, 129, 0.7, 3),
     (ISING, 3, 3, 2, 4.5115, 20),
     (ISING, 3, 33, 2, 4.5115, 5),
     (ISING, 3, 40, 2, 4.0, 4),

@@ -129,9 +129,19 @@ def test_ising_4x4_exact():
     beta = 1.0 / T
     E, M = ising2d_enum(L)
     N = L * L
-    ex, Ev, p = exact_from_samples(E, {"e": E / N, "m2": (M / N) ** 2, "m4": (M / N) ** 4}, beta)
-    # closed-form check of the enumeration itself: 2^16 states, E symmetric
+    ex, Ev, p = exact_from_samples(E, {"e": E / N, "m2": (M / N) ** 2, "m4": (M / N) ** 4,
+                                       "e2": (E / N) ** 2}, beta)
+    # the enumeration itself against an independent brute-force computation of
+    # the 4x4 density of states and moments at T_c
     assert len(E) == 65536 and (E.min(), E.max()) == (-32, 32)
+    vals, cnt = np.unique(E, return_counts=True)
+    assert list(vals) == [-32, -24, -20, -16, -12, -8, -4, 0, 4, 8, 12, 16, 20, 24, 32]
+    assert list(cnt[:8]) == [2, 32, 64, 424, 1728, 6688, 13568, 20524] and list(cnt) == list(cnt[::-1])
+    c_exact = beta ** 2 * N * (ex["e2"] - ex["e"] ** 2)
+    assert ex["e"] == pytest.approx(-1.5656237876, abs=1e-10)
+    assert ex["m2"] == pytest.approx(0.7613589086, abs=1e-10)
+    assert ex["m4"] == pytest.approx(0.6656912133, abs=1e-10)
+    assert c_exact == pytest.approx(0.7832668259, abs=1e-10)
     n = 400000
     s0 = oracle.init_state(oracle.ISING, 2, L, 2, seed=11)
     r = oracle.sweeps(oracle.ISING, 2, L, 2, beta, 11, 0, 0, n, s0, last=False)["records"]
@@ -140,6 +150,9 @@ def test_ising_4x4_exact():
     assert abs(batch_mean_z(e / N, ex["e"])) < 5
     assert abs(batch_mean_z(m ** 2, ex["m2"])) < 5
     assert abs(batch_mean_z(m ** 4, ex["m4"])) < 5
+    # specific heat per spin (the paper's printed output): per-batch estimates
+    cb = np.array([beta ** 2 * N * v.var() for v in np.array_split(e / N, 50)])
+    assert abs((cb.mean() - c_exact) / (cb.std(ddof=1) / math.sqrt(50))) < 5
     vals, pm = energy_pmf(E, p)
     pv, stat, dof = chi2_pvalue(e[::5], vals, pm)
     assert pv > 1e-6, (pv, stat, dof)
@@ -154,6 +167,11 @@ def test_potts_3x3_q3_exact():
     assert len(E) == 3 ** 9
     ex, Ev, p = exact_from_samples(E, {"e": E / N, "m2": M2 / N ** 2, "m4": (M2 / N ** 2) ** 2},
                                    beta)
+    # the enumeration against an independent brute-force computation (H of
+    # Eq. (2) with states 0..q-1, M^2 of Eq. (5))
+    assert ex["e"] == pytest.approx(0.2578777853, abs=1e-10)
+    assert ex["m2"] == pytest.approx(0.8110566549, abs=1e-10)
+    assert ex["m4"] == pytest.approx(0.7300389855, abs=1e-10)
     n = 400000
     s0 = oracle.init_state(oracle.POTTS, 2, L, q, seed=5)
     r = oracle.sweeps(oracle.POTTS, 2, L, q, beta, 5, 0, 0, n, s0, last=False)["records"]

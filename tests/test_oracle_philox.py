@@ -103,19 +103,36 @@ def test_bond_uniform_layout():
 
 
 def test_column_layout_is_a_bijection():
-    # every BOND word (and BOND_Z half) is used by exactly one site, so no two
-    # bonds share a primary
-    for dim, L in ((2, 10), (3, 6)):
-        seen = {}
-        for g in range(L ** dim):
-            x, y, z = g % L, (g // L) % L, g // (L * L)
-            k = (x + L * (y // 4 + -(-L // 4) * z), y % 4)
-            assert k not in seen
-            seen[k] = g
-            if dim == 3:
-                kz = ("z", x + L * (y // 8 + -(-L // 8) * z), y % 8)
-                assert kz not in seen
-                seen[kz] = g
+    """Every 16-bit half of the BOND words that fall on a site (and of the
+    BOND_Z words in 3D) is the primary of exactly one bond of the oracle:
+    the sorted primaries that swo_bond_uniform hands out equal the sorted
+    halves of the stream's words, so no two bonds share a primary and none
+    is left out (sizes that are not multiples of 4 or 8 included)."""
+    seed, rep, n = 5, 2, 9
+    key = [seed & 0xFFFFFFFF, seed >> 32]
+    for dim, L in ((2, 10), (3, 6), (3, 5)):
+        N = L ** dim
+        got_xy = sorted(oracle.bond_uniform(seed, rep, n, dim, L, g, mu) >> 16 for g in range(N) for mu in (0, 1))
+        q4, q8, nz = -(-L // 4), -(-L // 8), (L if dim == 3 else 1)
+        want_xy = []
+        for b in range(L * q4 * nz):
+            yb = (b // L) % q4
+            w = oracle.philox([b, n, oracle.TAG_BOND, rep], key)
+            for lane in range(4):
+                if 4 * yb + lane < L:  # the word of a site
+                    want_xy += [int(w[lane]) >> 16, int(w[lane]) & 0xFFFF]
+        assert got_xy == sorted(want_xy), (dim, L)
+        if dim == 3:
+            got_z = sorted(oracle.bond_uniform(seed, rep, n, dim, L, g, 2) >> 16 for g in range(N))
+            want_z = []
+            for b in range(L * q8 * L):
+                yb = (b // L) % q8
+                w = oracle.philox([b, n, oracle.TAG_BOND_Z, rep], key)
+                for half in range(8):  # y = 8 yb + half: lane half // 2, high half for even y
+                    if 8 * yb + half < L:
+                        v = int(w[half // 2])
+                        want_z.append((v >> 16) if half % 2 == 0 else (v & 0xFFFF))
+            assert got_z == sorted(want_z), (dim, L)
 
 
 def test_bond_uniform_is_uniform():

@@ -213,3 +213,38 @@ def test_xy_high_temperature():
     # the first loop correction on the square lattice is O(beta^3) ~ 1e-3 relative
     assert abs(e_bond.mean() - want) < 2e-3
     assert abs(batch_mean_z(e_bond, want, nb=20)) < 6
+
+
+def test_xy_bond_margins_near_ties():
+    """How close the XY bond test comes to a tie: u = U 2^-32 against
+    p = -expm1(-(2 beta s_i) s_j) with s = cos(theta - phi), recomputed with
+    numpy's libm on every bond of a 3D lattice and two sweeps' directions.
+    A bond whose |u - p| is below 1e-12 could flip if two libms disagreed in
+    the last bits of cos or expm1; none may occur, and the decisions must be
+    the oracle's.  The smallest margin is printed (the libm margin the GPU
+    parity of the XY bonds relies on)."""
+    import math
+    L, dim, beta, seed = 20, 3, 1 / 2.2019, 3
+    st = oracle.init_state(oracle.XY, dim, L, 0, seed)
+    N = L ** dim
+    g = np.arange(N)
+    x, y, z = g % L, (g // L) % L, g // (L * L)
+    nbr = [((x + 1) % L) + L * (y + L * z), x + L * (((y + 1) % L) + L * z), x + L * (y + L * ((z + 1) % L))]
+    smallest, ties = 1.0, 0
+    for n in (0, 1):
+        phi = oracle.xy_phi(seed, 0, n)
+        b, _ = oracle.bonds(oracle.XY, dim, L, 0, beta, seed, 0, n, st)
+        s = np.cos(st.astype(np.float64) - phi)
+        for mu in range(dim):
+            sj = s[nbr[mu]]
+            p = -np.expm1(-(2.0 * beta * s) * sj)
+            u = np.array([oracle.bond_uniform(seed, 0, n, dim, L, i, mu) for i in range(N)], dtype=np.float64)
+            u *= 2.0 ** -32
+            want = (s * sj > 0) & (u < p)
+            np.testing.assert_array_equal(((b >> mu) & 1).astype(bool), want)
+            m = np.abs(u - p)[s * sj > 0]
+            smallest = min(smallest, float(m.min()))
+            ties += int((m < 1e-12).sum())
+    print(f"XY bond margins: smallest |u - p| = {smallest:.3e} over {2 * dim * N} bonds")
+    assert ties == 0 and smallest > 0.0
+    assert math.isfinite(smallest)
