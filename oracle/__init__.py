@@ -15,9 +15,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsworacle.so")
 SRC = os.path.join(HERE, "sw_oracle.c")
 
-ISING, POTTS, XY = 0, 1, 2
+ISING, POTTS, XY, CLOCK = 0, 1, 2, 3
 TAG_BOND, TAG_BOND_Z, TAG_BOND_TIE, TAG_CLUSTER, TAG_GLOBAL, TAG_INIT = range(6)
-STATE_DTYPE = {ISING: np.int8, POTTS: np.uint8, XY: np.float32}
+STATE_DTYPE = {ISING: np.int8, POTTS: np.uint8, XY: np.float32, CLOCK: np.uint16}
 
 
 def build(force=True):
@@ -61,6 +61,13 @@ def lib():
         L.swo_set_clusters.argtypes = [i32, i32, i32, i32, u64, u32, u32, vp, vp]
         L.swo_measure.argtypes = [i32, i32, i32, i32, vp, vp, vp, vp, vp, vp]
         L.swo_cluster_stats.argtypes = [i64, vp, vp]
+        L.swo_clock_axis.argtypes = [u64, u32, u32, i32]
+        L.swo_clock_axis.restype = u32
+        L.swo_clock_projection.argtypes = [i32, u32, u32, vp, vp]
+        L.swo_clock_threshold.argtypes = [i32, dbl, i32, i32]
+        L.swo_clock_threshold.restype = u64
+        L.swo_clock_mirror.argtypes = [i32, u32, u32]
+        L.swo_clock_mirror.restype = ctypes.c_uint16
         L.swo_sweeps.argtypes = [i32, i32, i32, i32, dbl, u64, u32, u32, i64, vp,
                                  vp, vp, vp, vp, vp, vp, vp]
         _lib = L
@@ -107,6 +114,24 @@ def init_state(model, dim, L, q, seed, rep=0):
 
 def xy_phi(seed, rep, sweep):
     return float(lib().swo_xy_phi(seed, rep, sweep))
+
+
+def clock_axis(seed, rep, sweep, q):
+    return int(lib().swo_clock_axis(seed, rep, sweep, q))
+
+
+def clock_projection(q, p, r):
+    m, s = ctypes.c_int(), ctypes.c_int()
+    lib().swo_clock_projection(q, p, r, ctypes.byref(m), ctypes.byref(s))
+    return m.value, s.value
+
+
+def clock_threshold(q, beta, m1, m2):
+    return int(lib().swo_clock_threshold(q, float(beta), m1, m2))
+
+
+def clock_mirror(q, p, r):
+    return int(lib().swo_clock_mirror(q, p, r))
 
 
 def bonds(model, dim, L, q, beta, seed, rep, sweep, state):

@@ -52,6 +52,25 @@
  *       with thr = floor(p * 2^32).
  *   R9  J = k_B = 1, beta = 1/T; any L >= 3 (the paper's multiple of 32 is a
  *       constraint of its kernels, not of the method).
+ *   R13 the q-state clock model, the paper's own XY path (Sec. 2, XY
+ *       paragraph; Sec. 3 uses q = 512): integer states p in [0, q), spin
+ *       angle 2 pi p / q, q even and at most 512 (the paper's table limit),
+ *       H = -J sum cos(2 pi (p_i - p_j) / q) (Eq. (3) on the clock angles).
+ *       The random mirror direction `ispr` is the axis index
+ *       r = floor(w q / 2^32) of word 0 of GLOBAL at the sweep, the axis at
+ *       angle phi = pi r / q (the q axes that map the clock onto itself; the
+ *       half-step axes are needed, else the parity of p would never change).
+ *       Projection sigma = cos(theta - phi) = cos(pi a / q) with
+ *       a = (2 p - r) mod 2q, taken from one table c[m] = cos(pi m / q),
+ *       0 <= m < q/2: fold a to a1 = min(a, 2q - a); sigma = c[a1] for
+ *       a1 < q/2, 0 for a1 = q/2, -c[q - a1] beyond.  A bond is active iff
+ *       both projections are nonzero with equal signs and U < thr(m_i, m_j),
+ *       thr = floor(p 2^32) (capped at 2^32 - 1) with
+ *       p = -expm1(-(2 beta) (c[m_i] c[m_j])): an integer test, like Ising's.
+ *       A cluster is mirrored with probability 1/2 (decision bit as XY):
+ *       p -> (q/2 + r - p) mod q, the image of theta -> pi + 2 phi - theta.
+ *       Measured: E with the paper's energy table rule[k] = cos(2 pi k / q)
+ *       over k = (p_i - p_j) mod q, and Mx, My from cos, sin of 2 pi p / q.
  */
 #include "sw_oracle.h"
 
@@ -194,6 +213,8 @@ void swo_init_state(int model, int dim, int L, int q, uint64_t seed, uint32_t re
             ((int8_t *)state)[i] = (w >> 31) ? (int8_t)-1 : (int8_t)1;
         } else if (model == SWO_POTTS) {
             ((uint8_t *)state)[i] = (uint8_t)(((uint64_t)w * (uint64_t)q) >> 32);
+        } else if (model == SWO_CLOCK) {
+            ((uint16_t *)state)[i] = (uint16_t)(((uint64_t)w * (uint64_t)q) >> 32);
         } else {
             ((float *)state)[i] = xy_angle_from_unit((double)w * 0x1p-32);
         }
@@ -212,6 +233,54 @@ double swo_xy_phi(uint64_t seed, uint32_t rep, uint32_t sweep)
 }
 
 /* ------------------------------------------------------------------------ */
+/* Clock model (R13): mirror axis, projections, bond thresholds, mirror.      */
+/* ------------------------------------------------------------------------ */
+uint32_t swo_clock_axis(uint64_t seed, uint32_t rep, uint32_t sweep, int q)
+{
+    uint32_t w = swo_word(seed, rep, SWO_TAG_GLOBAL, sweep, 0);
+    return (uint32_t)(((uint64_t)w * (uint64_t)q) >> 32);
+}
+
+/* cos(pi m / q), the projection of a clock spin at angular distance m pi / q
+ * from the axis, 0 <= m < q/2. */
+static double clock_c(int q, int m)
+{
+    return cos((PI_D * (double)m) / (double)q);
+}
+
+/* Fold the projection index a = (2p - r) mod 2q: *m in [0, q/2] and the sign
+ * of sigma (+1, -1, or 0 when the spin is perpendicular to the axis). */
+void swo_clock_projection(int q, uint32_t p, uint32_t r, int *m, int *sign)
+{
+    int a = (int)((2u * p + 2u * (uint32_t)q - r) % (2u * (uint32_t)q));
+    int a1 = a <= q ? a : 2 * q - a;
+    if (2 * a1 < q) {
+        *m = a1;
+        *sign = 1;
+    } else if (2 * a1 == q) {
+        *m = q / 2;
+        *sign = 0;
+    } else {
+        *m = q - a1;
+        *sign = -1;
+    }
+}
+
+uint64_t swo_clock_threshold(int q, double beta, int m1, int m2)
+{
+    double x = (2.0 * beta) * (clock_c(q, m1) * clock_c(q, m2));
+    double p = -expm1(-x);
+    if (!(p > 0.0)) return 0;
+    double t = floor(ldexp(p, 32));
+    return t >= 4294967295.0 ? 4294967295ull : (uint64_t)t;
+}
+
+uint16_t swo_clock_mirror(int q, uint32_t p, uint32_t r)
+{
+    return (uint16_t)(((uint32_t)(q / 2) + r + (uint32_t)q - p) % (uint32_t)q);
+}
+
+/* ------------------------------------------------------------------------ */
 /* Step (1): active-bond generation (Sec. 2).                                 */
 /*   Ising/Potts: aligned pair and u < p.                                     */
 /*   XY: project on the mirror direction, sigma = cos(theta - phi); the       */
@@ -223,13 +292,15 @@ double swo_xy_phi(uint64_t seed, uint32_t rep, uint32_t sweep)
 int64_t swo_bonds(int model, int dim, int L, int q, double beta, uint64_t seed, uint32_t rep,
                   uint32_t sweep, const void *state, uint8_t *bonds)
 {
-    (void)q;
     int64_t N = num_sites(dim, L);
     int64_t active = 0;
     double *sigma = NULL;
     double two_beta = 2.0 * beta;
     uint64_t thr = 0;
-    if (model == SWO_XY) {
+    uint32_t axis = 0;
+    if (model == SWO_CLOCK) {
+        axis = swo_clock_axis(seed, rep, sweep, q);
+    } else if (model == SWO_XY) {
         double phi = swo_xy_phi(seed, rep, sweep);
         const float *th = (const float *)state;
         sigma = (double *)malloc(sizeof(double) * (size_t)N);
@@ -249,6 +320,12 @@ int64_t swo_bonds(int model, int dim, int L, int q, double beta, uint64_t seed, 
             } else if (model == SWO_POTTS) {
                 const uint8_t *s = (const uint8_t *)state;
                 on = (s[i] == s[j]) && ((uint64_t)w < thr);
+            } else if (model == SWO_CLOCK) {
+                const uint16_t *s = (const uint16_t *)state;
+                int mi, si, mj, sj;
+                swo_clock_projection(q, s[i], axis, &mi, &si);
+                swo_clock_projection(q, s[j], axis, &mj, &sj);
+                on = si != 0 && si == sj && (uint64_t)w < swo_clock_threshold(q, beta, mi, mj);
             } else {
                 double x = (two_beta * sigma[i]) * sigma[j];
                 double p = -expm1(-x);
@@ -361,12 +438,16 @@ void swo_set_clusters(int model, int dim, int L, int q, uint64_t seed, uint32_t 
 {
     int64_t N = num_sites(dim, L);
     double phi = (model == SWO_XY) ? swo_xy_phi(seed, rep, sweep) : 0.0;
+    uint32_t axis = (model == SWO_CLOCK) ? swo_clock_axis(seed, rep, sweep, q) : 0u;
     for (int64_t i = 0; i < N; ++i) {
         uint32_t dec = swo_cluster_decision(model, q, seed, rep, sweep, dim, L, (uint64_t)labels[i]);
         if (model == SWO_ISING) {
             ((int8_t *)state)[i] = dec ? (int8_t)-1 : (int8_t)1;
         } else if (model == SWO_POTTS) {
             ((uint8_t *)state)[i] = (uint8_t)dec;
+        } else if (model == SWO_CLOCK) {
+            uint16_t *p = (uint16_t *)state;
+            if (dec) p[i] = swo_clock_mirror(q, p[i], axis);
         } else if (dec) {
             float *th = (float *)state;
             th[i] = xy_reflect(th[i], phi);
@@ -416,6 +497,24 @@ void swo_measure(int model, int dim, int L, int q, const void *state, double *en
         if (counts)
             for (int k = 0; k < q; ++k) counts[k] = n[k];
         free(n);
+    } else if (model == SWO_CLOCK) {
+        const uint16_t *p = (const uint16_t *)state;
+        double *rule = (double *)malloc(sizeof(double) * (size_t)q);
+        double *sn = (double *)malloc(sizeof(double) * (size_t)q);
+        for (int k = 0; k < q; ++k) {
+            rule[k] = cos((TWO_PI_D * (double)k) / (double)q);
+            sn[k] = sin((TWO_PI_D * (double)k) / (double)q);
+        }
+        for (int64_t i = 0; i < N; ++i) {
+            sx += rule[p[i]];
+            sy += sn[p[i]];
+            for (int mu = 0; mu < dim; ++mu) {
+                int64_t j = neighbour(dim, L, i, mu);
+                e -= rule[((int)p[i] - (int)p[j] + q) % q];
+            }
+        }
+        free(rule);
+        free(sn);
     } else {
         const float *th = (const float *)state;
         for (int64_t i = 0; i < N; ++i) {

@@ -14,7 +14,8 @@
  *            site index i = x + L*(y + L*z), x fastest.
  *   bonds    bonds[i] bit mu = bond between i and its +mu neighbour.
  *   states   Ising: int8 +1/-1.  Potts: uint8 in [0,q).  XY: float angle in
- *            [0, (float)2pi).
+ *            [0, (float)2pi).  Clock (q even, <= 512): uint16 p in [0,q),
+ *            angle 2 pi p / q.
  *   labels   int32, label[i] = minimum site index of i's cluster.
  */
 #ifndef SW_ORACLE_H
@@ -25,7 +26,7 @@
 extern "C" {
 #endif
 
-enum { SWO_ISING = 0, SWO_POTTS = 1, SWO_XY = 2 };
+enum { SWO_ISING = 0, SWO_POTTS = 1, SWO_XY = 2, SWO_CLOCK = 3 };
 enum {
     SWO_TAG_BOND = 0, SWO_TAG_BOND_Z = 1, SWO_TAG_BOND_TIE = 2,
     SWO_TAG_CLUSTER = 3, SWO_TAG_GLOBAL = 4, SWO_TAG_INIT = 5
@@ -58,6 +59,14 @@ void swo_init_state(int model, int dim, int L, int q, uint64_t seed, uint32_t re
 /* Embedding direction of the XY update at sweep n. */
 double swo_xy_phi(uint64_t seed, uint32_t rep, uint32_t sweep);
 
+/* Clock model: mirror axis index r of sweep n, the folded projection of
+ * state p on it (index m into cos(pi m / q) and its sign), the integer bond
+ * threshold of two projections, and the mirror image of p. */
+uint32_t swo_clock_axis(uint64_t seed, uint32_t rep, uint32_t sweep, int q);
+void swo_clock_projection(int q, uint32_t p, uint32_t r, int *m, int *sign);
+uint64_t swo_clock_threshold(int q, double beta, int m1, int m2);
+uint16_t swo_clock_mirror(int q, uint32_t p, uint32_t r);
+
 /* Step (1): bond lattice for sweep n from `state`; returns #active bonds. */
 int64_t swo_bonds(int model, int dim, int L, int q, double beta, uint64_t seed,
                   uint32_t rep, uint32_t sweep, const void *state, uint8_t *bonds);
@@ -71,9 +80,10 @@ void swo_set_clusters(int model, int dim, int L, int q, uint64_t seed, uint32_t 
                       uint32_t sweep, const int32_t *labels, void *state);
 
 /* Observables of one configuration.
- *   energy : H with J = 1 (Ising -sum s s; Potts sum (1 - delta); XY -sum cos)
+ *   energy : H with J = 1 (Ising -sum s s; Potts sum (1 - delta); XY and
+ *            clock -sum cos)
  *   mx, my : Ising (sum s, 0); Potts (M^2 of the Potts definition, 0);
- *            XY (sum cos, sum sin)
+ *            XY and clock (sum cos, sum sin)
  *   aligned: number of bonds joining equal states (Ising/Potts), else 0
  *   counts : Potts only, q entries n[k] (may be NULL) */
 void swo_measure(int model, int dim, int L, int q, const void *state, double *energy,
