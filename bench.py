@@ -4,15 +4,21 @@ Default workload: 2D q=3 Potts and 2D Ising, L = 4096, periodic, at their
 exact critical temperatures, hot start, plain form (one lattice per launch).
 A step is one SW sweep of every lattice of the workload (bond generation +
 tile labelling, label merge, cluster flip, per-sweep measurement).  Prints one
-JSON line with spin updates/ns, the HBM roofline of the dominant kernel and
-the oracle timed on the host as a CPU baseline.
+JSON line with spin updates/ns, the HBM roofline of the dominant kernel, a
+per-kernel block (bond, global labelling, flip), the oracle timed on the
+host's cores as a CPU baseline, and compact figures of the other workloads:
+3D Ising L=256 (plain), 3D XY 32 x 128^3 (batched), the paper's 512-state
+clock model on its Table 2 shape (3D L=256), and the served job mix (at the
+configured 200 jobs/s and at a rate the server sustains, with the same jobs
+run back to back in the plain form).
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config C2|C1|C3|C4|C5]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config C2|C1|C3|C4|C5|CLOCK]
+                    [--labeller 0|1|2] [--quick]
 
-C5 is the served form: a seeded Poisson job mix (--jobs, --rate) replayed in
-wall-clock time against the continuous-batching server, reporting served
-throughput, p50/p99 job latency (arrival to last sweep) and the same jobs
-run back to back in the plain form.
+C5 alone is the served form: a seeded Poisson job mix (--jobs, --rate)
+replayed in wall-clock time against the continuous-batching server,
+reporting served throughput, p50/p99 job latency (arrival to last sweep) and
+the same jobs run back to back in the plain form.
 """
 import argparse
 import hashlib
@@ -34,6 +40,7 @@ WORKLOADS = {
     "C3": ["C3"],
     "C4": ["C4"],
     "C5": [],
+    "CLOCK": ["CLOCK-512"],
 }
 DESCRIPTION = {
     "C1": "2D Ising L=64 T=2.269185 seed 1, plain form",
@@ -43,6 +50,13 @@ DESCRIPTION = {
     "C4": "3D XY L=128, 32 replicas over [0.95 Tc, 1.05 Tc], batched form",
     "C5": "served job mix (2D Ising, 2D Potts q in {3,4,10}, 3D Ising, 3D XY; L log-uniform; "
           "100-5000 sweeps), Poisson arrivals, continuous batching",
+    "CLOCK": "3D 512-state clock model L=256 T=2.20175 (the paper's Table 2 shape), plain form",
+}
+# the paper's own figures for the same shapes (GTX580, update + measurement
+# rows of Tables 1 and 2): context only, another machine
+PAPER_CONTEXT = {
+    "C3": {"updates_per_ns": 0.300, "source": "Table 1, 3D Ising L=256, update + measurement, GTX580"},
+    "CLOCK": {"updates_per_ns": 0.223, "source": "Table 2, 3D XY (q=512 clock) L=256, update + measurement, GTX580"},
 }
 
 
@@ -50,14 +64,30 @@ def algorithmic_bytes_per_site(model):
     # k_bond applies the previous sweep's cluster decisions as it reads the
     # incoming configuration: it reads the previous sweep's int32 label and
     # writes the bond byte and the new int32 label; XY also reads the
-    # previous working angle and writes the new one (FP32).
-    return 4 + 1 + 4 + (8 if model == 2 else 0)
+    # previous working angle and writes the new one (FP32), the clock model
+    # its state index (16 bits).
+    return 4 + 1 + 4 + {2: 8, 3: 4}.get(model, 0)
+
+
+def flip_bytes_per_site(model):
+    # k_flip reads the label word and writes the state (1 B; the clock model
+    # reads its working state index and writes the state, 2 + 2 B; XY 4 + 4 B)
+    return 4 + {2: 8, 3: 4}.get(model, 1)
+
+
+def merge_bytes_per_launch(lat):
+    # the global phase reads both sides of every tile face (two int32 slots
+    # per face element); the label words it touches are a few per cluster
+    # crossing a face, not counted
+    return 8 * lat.face_elements()
 
 
 def kernel_source_hash():
-    src = os.path.join(ROOT, "paper_1403_7560_amd", "csrc", "sw_kernels.hip")
-    with open(src, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in ("sw_bond.h", "sw_device.h", "sw_internal.h"):
+        with open(os.path.join(ROOT, "paper_1403_7560_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def load_traffic(config, bytes_per_launch_alg):
@@ -73,25 +103,44 @@ def load_traffic(config, bytes_per_launch_alg):
     return t.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(config, lattices):
-    """The oracle (single-threaded C) on a bounded sample of the workload."""
-    import numpy as np
+def _oracle_sample(args):
+    """One oracle chain (a worker of the CPU baseline): sweeps from the hot
+    start of lattice j; returns (updates, seconds)."""
+    j, sweeps = args
     import oracle
+    s0 = oracle.init_state(j["model"], j["dim"], j["L"], j["q"], j["seed"], j["replica"])
+    t0 = time.perf_counter()
+    oracle.sweeps(j["model"], j["dim"], j["L"], j["q"], j["beta"], j["seed"], j["replica"], 0,
+                  sweeps, s0, record=True, last=False)
+    return j["L"] ** j["dim"] * sweeps, time.perf_counter() - t0
+
+
+def cpu_baseline(config, lattices):
+    """The oracle (single-threaded C, as it stands) on a bounded sample of the
+    workload: first one chain on one core, then one independent chain per
+    host core at once (replicas with their own replica index), whose
+    aggregate rate is the baseline.  Runs before anything touches the GPU:
+    the workers are forked."""
+    import multiprocessing as mp
+    import oracle
+    oracle.build(force=False)
     if config == "C4":
         lattices = lattices[:1]
     sweeps = 200 if config == "C1" else 1
+    names = ", ".join(f"{['Ising', 'Potts', 'XY', 'clock'][j['model']]} {j['dim']}D L={j['L']}" for j in lattices)
+    one = [_oracle_sample((j, sweeps)) for j in lattices]
+    v1 = sum(u for u, _ in one) / (sum(t for _, t in one) * 1e9)
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    jobs = [(dict(lattices[r % len(lattices)], replica=1000 + r), sweeps) for r in range(cores)]
     t0 = time.perf_counter()
-    updates = 0
-    for j in lattices:
-        s0 = oracle.init_state(j["model"], j["dim"], j["L"], j["q"], j["seed"], j["replica"])
-        oracle.sweeps(j["model"], j["dim"], j["L"], j["q"], j["beta"], j["seed"], j["replica"], 0,
-                      sweeps, s0, record=True, last=False)
-        updates += j["L"] ** j["dim"] * sweeps
-    dt = time.perf_counter() - t0
-    names = ", ".join(f"{'Ising' if j['model'] == 0 else 'Potts' if j['model'] == 1 else 'XY'}"
-                      f" {j['dim']}D L={j['L']}" for j in lattices)
-    return {"value": updates / (dt * 1e9), "unit": "spin updates/ns", "cores": 1, "kind": "oracle",
-            "sample": f"{sweeps} sweep(s) from hot start of each of: {names}; {dt:.1f} s"}
+    with mp.get_context("fork").Pool(cores) as pool:
+        res = pool.map(_oracle_sample, jobs)
+    wall = time.perf_counter() - t0
+    upd = sum(u for u, _ in res)
+    return {"value": upd / (wall * 1e9), "unit": "spin updates/ns", "cores": cores, "kind": "oracle",
+            "sample": f"{cores} independent oracle chains at once, one per host core, each {sweeps} sweep(s) "
+                      f"from the hot start of one of: {names}; {wall:.1f} s wall",
+            "one_core": {"value": v1, "cores": 1, "seconds": round(sum(t for _, t in one), 2)}}
 
 
 def served(n_jobs, rate, seed=2014, plain=True):
@@ -157,6 +206,69 @@ def served(n_jobs, rate, seed=2014, plain=True):
     return out
 
 
+def timed_plain(sw, lattices, W, K, labeller=None):
+    """W warm-up and K timed sweeps of each lattice in the plain form, with
+    HIP events (profile level 2) around the bond kernel and the global
+    labelling phase of every 16th sweep and around each call's flip.
+    Returns (updates/ns, seconds, per-kernel block, lattices)."""
+    lats = [sw.Lattice(j["model"], j["dim"], j["L"], j["q"], j["beta"], j["seed"], j["replica"])
+            for j in lattices]
+    if labeller is not None:
+        for lat in lats:
+            lat.set_labeller(labeller, 256)
+    for lat in lats:
+        lat.sweep(W)
+    for lat in lats:
+        lat.profile(2)
+    t0 = time.perf_counter()
+    for lat in lats:
+        lat.sweep(K)
+    dt = time.perf_counter() - t0
+    total = 0
+    kb = {"k_bond": [0.0, 0, 0.0], "global_phase": [0.0, 0, 0.0], "k_flip": [0.0, 0, 0.0]}
+    for lat in lats:
+        p = lat.profile_read()
+        lat.profile(0)
+        total += lat.N * K
+        for name, key, per in (("k_bond", "bond", algorithmic_bytes_per_site(lat.model) * lat.N),
+                               ("global_phase", "merge", merge_bytes_per_launch(lat)),
+                               ("k_flip", "flip", flip_bytes_per_site(lat.model) * lat.N)):
+            kb[name][0] += p[key][0]
+            kb[name][1] += p[key][1]
+            kb[name][2] += per * p[key][1]
+    kernels = {}
+    for name, (ms, n, byts) in kb.items():
+        if n == 0:
+            continue
+        gbs = byts / (ms * 1e-3) / 1e9
+        kernels[name] = {"avg_us": round(ms * 1e3 / n, 2), "launches_timed": n,
+                         "algorithmic_bytes_per_launch": int(byts / n),
+                         "achieved_GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    return total / (dt * 1e9), dt, kernels, lats
+
+
+def leg_plain(sw, inputs, name, W, K, labeller=None):
+    lattices, _ = inputs.workload(name)
+    v, dt, kernels, lats = timed_plain(sw, lattices, W, K, labeller)
+    for lat in lats:
+        lat.close()
+    return {"value": round(v, 3), "unit": "spin updates/ns", "ms_per_sweep": round(dt * 1e3 / K, 4),
+            "steps": K, "warmup": W, "kernels": kernels}
+
+
+def leg_batched(sw, inputs, name, W, K):
+    lattices, _ = inputs.workload(name)
+    b = sw.Batch(lattices)
+    b.sweep(W)
+    t0 = time.perf_counter()
+    b.sweep(K)
+    dt = time.perf_counter() - t0
+    b.close()
+    total = sum(j["L"] ** j["dim"] for j in lattices) * K
+    return {"value": round(total / (dt * 1e9), 3), "unit": "spin updates/ns",
+            "ms_per_step": round(dt * 1e3 / K, 4), "steps": K, "warmup": W, "lattices": len(lattices)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -164,6 +276,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--config", default="C2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--quick", action="store_true", help="skip the secondary workloads of the default line")
+    ap.add_argument("--labeller", type=int, default=None, choices=(0, 1, 2),
+                    help="plain form: global labelling phase (0 Hawick, 1 Kalentev, 2 union)")
     ap.add_argument("--jobs", type=int, default=300, help="C5: jobs in the replayed trace")
     ap.add_argument("--rate", type=float, default=200.0, help="C5: arrivals per second")
     ap.add_argument("--no-plain", action="store_true", help="C5: skip the plain-form replay of the same jobs")
@@ -176,8 +291,19 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    import paper_1403_7560_amd as sw
     from paper_1403_7560_amd import inputs
+    lattices = []
+    default_steps = None
+    for name in WORKLOADS[args.config]:
+        lats, n = inputs.workload(name)
+        lattices += lats
+        default_steps = n
+    # the CPU baseline forks its workers, so it runs before the GPU is touched
+    cpu = None
+    if args.config != "C5" and not args.no_cpu_baseline:
+        cpu = cpu_baseline(args.config, lattices)
+
+    import paper_1403_7560_amd as sw
 
     if args.copy_probe:
         # a plain copy of known size: reads and writes copy_probe bytes, for
@@ -208,60 +334,32 @@ def main():
         print(json.dumps(out), flush=True)
         return
 
-    lattices = []
-    default_steps = None
-    for name in WORKLOADS[args.config]:
-        lats, n = inputs.workload(name)
-        lattices += lats
-        default_steps = n
     K = args.steps if args.steps is not None else default_steps
     W = args.warmup
 
-    prof = {k: [0.0, 0] for k in KERNELS}
-    alg_bytes = 0
-    n_bond = 0
+    kernels = None
     if args.config == "C4":
         b = sw.Batch(lattices)
         b.sweep(W)
         t0 = time.perf_counter()
         b.sweep(K)
         dt = time.perf_counter() - t0
+        b.close()
         total = sum(j["L"] ** j["dim"] for j in lattices) * K
+        value = total / (dt * 1e9)
         roof = None
     else:
-        lats = [sw.Lattice(j["model"], j["dim"], j["L"], j["q"], j["beta"], j["seed"], j["replica"])
-                for j in lattices]
+        value, dt, kernels, lats = timed_plain(sw, lattices, W, K, args.labeller)
         for lat in lats:
-            lat.sweep(W)
-        for lat in lats:
-            lat.profile(1)  # HIP events around the k_bond launch of every 16th sweep of the timed region
-        t0 = time.perf_counter()
-        for lat in lats:
-            lat.sweep(K)
-        dt = time.perf_counter() - t0
-        total = 0
-        for lat in lats:
-            p = lat.profile_read()
-            lat.profile(0)
-            for k in KERNELS:
-                prof[k][0] += p[k][0]
-                prof[k][1] += p[k][1]
-            total += lat.N * K
-            # the timed launches only (every 16th sweep)
-            alg_bytes += algorithmic_bytes_per_site(lat.model) * lat.N * p["bond"][1]
-            n_bond += p["bond"][1]
-        bond_ms = prof["bond"][0]
-        achieved = alg_bytes / (bond_ms * 1e-3) / 1e9
-        per_launch = alg_bytes / max(n_bond, 1)
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": load_traffic(args.config, per_launch),
+            lat.close()
+        kb = kernels["k_bond"]
+        roof = {"bound": "hbm", "achieved": kb["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": kb["frac"],
+                "traffic": load_traffic(args.config, kb["algorithmic_bytes_per_launch"]),
                 "kernel": "k_bond (bond generation + tile labelling)",
-                "algorithmic_bytes_per_launch": per_launch,
-                "avg_launch_us": round(bond_ms * 1e3 / max(n_bond, 1), 2),
-                "kernel_avg_us": {k: round(prof[k][0] * 1e3 / prof[k][1], 2) for k in KERNELS if prof[k][1]}}
+                "algorithmic_bytes_per_launch": kb["algorithmic_bytes_per_launch"],
+                "avg_launch_us": kb["avg_us"]}
 
-    value = total / (dt * 1e9)
     models = sorted({j["model"] for j in lattices})
     out = {
         "metric": "spin updates/ns",
@@ -280,10 +378,31 @@ def main():
                    "lattices": [{k: j[k] for k in ("model", "dim", "L", "q", "beta", "seed", "replica")}
                                 for j in lattices[:4]] + ([f"... {len(lattices)} lattices"]
                                                           if len(lattices) > 4 else []),
-                   "sweeps_per_lattice": K},
+                   "sweeps_per_lattice": K,
+                   "labeller": {None: "union", 0: "Hawick", 1: "Kalentev", 2: "union"}[args.labeller]},
         "roofline": roof,
-        "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline(args.config, lattices),
+        "kernels": kernels,
+        "cpu_baseline": cpu,
     }
+    if args.config in PAPER_CONTEXT:
+        out["paper_context"] = PAPER_CONTEXT[args.config]
+    if args.config == "C2" and not args.quick:
+        # the other workloads, compact (same step counts as the main line)
+        out["c3_plain"] = dict(leg_plain(sw, inputs, "C3", W, K), workload=DESCRIPTION["C3"],
+                               paper_context=PAPER_CONTEXT["C3"])
+        out["c4_batched"] = dict(leg_batched(sw, inputs, "C4", W, K), workload=DESCRIPTION["C4"])
+        out["clock_q512"] = dict(leg_plain(sw, inputs, "CLOCK-512", W, K), workload=DESCRIPTION["CLOCK"],
+                                 paper_context=PAPER_CONTEXT["CLOCK"])
+        c5 = {}
+        for tag, n_jobs, rate in (("at_200_per_s", 100, 200.0), ("at_20_per_s", 60, 20.0)):
+            r = served(n_jobs, rate, plain=(tag == "at_200_per_s"))
+            c5[tag] = {"value": round(r["value"], 3), "jobs": n_jobs, "rate_per_s": rate,
+                       "latency_s": r["latency_s"], "offered_load": r["offered_load"],
+                       "offered_over_served": r["offered_over_served"]}
+            if r["plain_form"]:
+                c5[tag]["plain_form"] = r["plain_form"]
+                c5[tag]["speedup_vs_plain"] = r["speedup_vs_plain"]
+        out["c5_served"] = dict(c5, workload=DESCRIPTION["C5"])
     print(json.dumps(out), flush=True)
 
 

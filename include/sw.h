@@ -7,6 +7,8 @@
  *   Ising   (Sec. 1, Eq. (1)),  states int8 +1/-1,
  *   Potts   (Sec. 1, Eq. (2)),  states uint8 in [0,q)  (paper: 1..q),
  *   XY      (Sec. 1, Eq. (3)),  states float angles in [0, (float)2pi),
+ *   clock   (the paper's XY path: Sec. 2, XY paragraph; Sec. 3 uses q = 512),
+ *           states uint16 p in [0, q), angle 2 pi p / q, q even, <= 512,
  * on 2D square and 3D simple-cubic lattices of linear size L with periodic
  * boundaries.  One sweep is the three steps of Sec. 2: (1) active-bond
  * generation, (2) cluster labelling (label equivalence, fixed point = minimum
@@ -45,6 +47,15 @@
  *               1-exp(-2 beta sigma_i sigma_j) on the projections
  *               sigma = cos(theta - phi) onto a random direction phi drawn
  *               once per sweep (Sec. 2, embedded-cluster paragraph).
+ *   clock       the mirror axis (the paper's `ispr`) of sweep n is
+ *               r = floor(w q / 2^32), w = word 0 of tag 4, at angle pi r / q;
+ *               sigma = cos(pi a / q), a = (2p - r) mod 2q, folded to
+ *               m in [0, q/2] with a sign; a bond needs equal nonzero signs
+ *               and U < thr(m_i, m_j) = floor(2^32 (1 - exp(-2 beta
+ *               cos(pi m_i/q) cos(pi m_j/q)))) (capped at 2^32 - 1): an
+ *               integer test.  A cluster whose decision bit is set is
+ *               mirrored, p -> (q/2 + r - p) mod q.  Records hold E (the
+ *               paper's rule table cos(2 pi k / q)), sum cos and sum sin.
  *
  * Errors: every int-returning call returns 0 (or a count) on success and a
  * negative SW_E_* code on failure; sw_last_error() gives a message for the
@@ -65,7 +76,7 @@
 extern "C" {
 #endif
 
-enum sw_model { SW_ISING = 0, SW_POTTS = 1, SW_XY = 2 };
+enum sw_model { SW_ISING = 0, SW_POTTS = 1, SW_XY = 2, SW_CLOCK = 3 };
 
 enum sw_status {
     SW_OK = 0,
@@ -101,7 +112,8 @@ typedef struct {
 
 /* Create a lattice and give it a hot start (every state drawn from the INIT
  * stream; the paper's spinset kernel).  model: SW_ISING (q ignored, use 2),
- * SW_POTTS (2 <= q <= 256), SW_XY (q ignored, use 0); dim 2 or 3; L >= 3 and
+ * SW_POTTS (2 <= q <= 256), SW_XY (q ignored, use 0), SW_CLOCK (even q,
+ * 2 <= q <= 512); dim 2 or 3; L >= 3 and
  * L^dim <= 2^31 - 1; beta >= 0 and finite.  Replica 0.  NULL on error. */
 sw_handle sw_create(int model, int dim, int L, int q, double beta, uint64_t seed);
 
@@ -209,12 +221,13 @@ const char *sw_last_error(void);
  * (bond generation + tile labelling; it also applies the previous sweep's
  * cluster decisions) of every sweep whose index is a multiple of 16 with HIP
  * events on the handle's stream and accumulates its duration and the number
- * of launches timed; level 2 also times those sweeps' label merge across
- * tiles; 0 turns it off.  Any level > 0 clears the totals.  SW_E_INVALID for
- * other levels. */
+ * of launches timed; level 2 also times those sweeps' global labelling phase
+ * (the label merge across tiles, or the iterative labeller) and the flip
+ * that ends each sw_sweep call; 0 turns it off.  Any level > 0 clears the
+ * totals.  SW_E_INVALID for other levels. */
 int sw_profile(sw_handle h, int on);
 /* Accumulated milliseconds and launch counts per kernel (3 entries each:
- * 0 = bond, 1 = merge, 2 = flip; the flip is not timed and stays 0). */
+ * 0 = bond, 1 = global labelling phase, 2 = flip). */
 int sw_profile_read(sw_handle h, double *ms, int64_t *launches);
 
 /* --- state access (checkpoint / parity hooks) ----------------------------- */

@@ -12,9 +12,9 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libswmc.so")
 
-ISING, POTTS, XY = 0, 1, 2
+ISING, POTTS, XY, CLOCK = 0, 1, 2, 3
 LABEL_HAWICK, LABEL_KALENTEV, LABEL_UNION = 0, 1, 2
-STATE_DTYPE = {ISING: np.int8, POTTS: np.uint8, XY: np.float32}
+STATE_DTYPE = {ISING: np.int8, POTTS: np.uint8, XY: np.float32, CLOCK: np.uint16}
 ERRORS = {-1: "SW_E_INVALID", -2: "SW_E_NOMEM", -3: "SW_E_DEVICE", -4: "SW_E_NOCONV",
           -5: "SW_E_BUSY", -6: "SW_E_NOTFOUND"}
 
@@ -170,6 +170,19 @@ class Lattice:
             self.close()
         except Exception:
             pass
+
+    def face_elements(self):
+        """Tile-face slots the global labelling phase reads per side (host
+        arithmetic on the tile shape)."""
+        ext = tile_shape(self.model, self.dim, self.tile)[:self.dim]
+        tiles = [-(-self.L // e) for e in ext]
+        nt = 1
+        for t in tiles:
+            nt *= t
+        T = 1
+        for e in ext:
+            T *= e
+        return sum(nt * (T // ext[mu]) for mu in range(self.dim) if tiles[mu] > 1)
 
     @property
     def tile(self):

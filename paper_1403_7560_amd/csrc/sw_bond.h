@@ -167,6 +167,63 @@ __device__ __forceinline__ uint32_t xy_bond_fast(double two_beta, double si, dou
 // ---------------------------------------------------------------------------
 template <int MODEL> struct LaneValue { typedef uint32_t type; };
 template <> struct LaneValue<XY> { typedef double type; };
+// What the working buffers hold between the sweeps of a chain: XY angles,
+// clock state indices (unused by Ising / Potts).
+template <int MODEL> struct WorkOf { typedef uint32_t type; };
+template <> struct WorkOf<XY> { typedef float type; };
+
+// Clock model: fold the projection index a = (2p - r) mod 2q of state p on
+// the mirror axis r to m in [0, q/2] and the projection's sign (+1, -1, 0
+// for a spin perpendicular to the axis): sigma = sign cos(pi m / q).
+__device__ __forceinline__ uint32_t clock_fold(uint32_t p, uint32_t r, uint32_t q, int &sgn)
+{
+    uint32_t a = 2u * p + 2u * q - r;  // in (0, 4q)
+    if (a >= 2u * q) a -= 2u * q;
+    const uint32_t a1 = a <= q ? a : 2u * q - a;
+    if (2u * a1 < q) {
+        sgn = 1;
+        return a1;
+    }
+    if (2u * a1 == q) {
+        sgn = 0;
+        return q >> 1;
+    }
+    sgn = -1;
+    return q - a1;
+}
+
+// Clock mirror of state p on axis r: (q/2 + r - p) mod q.
+__device__ __forceinline__ uint32_t clock_mirror(uint32_t p, uint32_t r, uint32_t q)
+{
+    uint32_t v = (q >> 1) + r + q - p;  // in (0, 2.5q)
+    if (v >= q) v -= q;
+    if (v >= q) v -= q;
+    return v;
+}
+
+// Mirror axis of sweep n: floor(w q / 2^32) of word 0 of the GLOBAL stream.
+__device__ __forceinline__ uint32_t clock_axis(const InstDesc &d, uint32_t n)
+{
+    const uint4 w = philox(make_uint4(0u, n, (uint32_t)TAG_GLOBAL, d.rep), d.key0, d.key1);
+    return (uint32_t)(((uint64_t)w.x * (uint64_t)(uint32_t)d.q) >> 32);
+}
+
+// Clock bond test: both projections nonzero with one sign, and the 32-bit
+// uniform (primary P, secondary on a tie) below the integer threshold of the
+// two projection indices (a table the host builds per (q, beta)).
+__device__ __forceinline__ uint32_t clock_bond(uint32_t pi, uint32_t pj, uint32_t r, const InstDesc &d,
+                                               uint32_t P, uint32_t gi, int mu, uint32_t key0, uint32_t key1,
+                                               uint32_t rep, uint32_t n, int dim)
+{
+    const uint32_t q = (uint32_t)d.q;
+    int si, sj;
+    const uint32_t mi = clock_fold(pi, r, q, si), mj = clock_fold(pj, r, q, sj);
+    if (si == 0 || si != sj) return 0u;
+    const uint32_t thr = d.clock_thr[mi * ((q >> 1) + 1u) + mj];
+    const uint32_t th = thr >> 16;
+    if (P != th) return P < th ? 1u : 0u;
+    return bond_secondary(key0, key1, rep, n, dim, gi, mu) < (thr & 0xffffu) ? 1u : 0u;
+}
 
 // Wavefronts per SIMD the bond kernel's registers are sized for: Ising /
 // Potts the hardware's 8 while a wavefront holds at most 16 rows (the LDS
@@ -175,6 +232,7 @@ template <> struct LaneValue<XY> { typedef double type; };
 template <int MODEL, int T, int NW> struct BondOccupancy {
     static constexpr int value = (MODEL == XY) ? 4 : ((T / NW <= 1024) ? 8 : 3);
 };
+// (the clock model keeps integer states and runs 8, like Ising)
 
 template <int MODEL, int DIM, int TX, int TY, int TZ, int NW, bool FULL>
 __global__ void __launch_bounds__(64 * NW, (BondOccupancy<MODEL, TX * TY * TZ, NW>::value))
@@ -188,6 +246,9 @@ k_bond(const InstDesc *__restrict__ descs,
     constexpr int R = ROWS / NW; // rows per wavefront
     constexpr int NG = R / 4;    // groups of four rows per wavefront
     constexpr bool IS_XY = (MODEL == XY);
+    constexpr bool IS_CK = (MODEL == CLOCK);
+    // XY and clock hold one value per row (no packed bytes of four rows)
+    constexpr bool VEC = IS_XY || IS_CK;
     constexpr int QCAP = 128;    // per-wave queue of deferred equivalences
     constexpr int NONE = 0x7fffffff;
     static_assert(TX == 64, "a tile row is one wavefront (lane = column)");
@@ -207,6 +268,9 @@ k_bond(const InstDesc *__restrict__ descs,
     __shared__ double s_red[NW][3];
     __shared__ double s_phi[4];  // XY: phi, cos phi, sin phi, previous sweep's phi
     __shared__ double2 s_cs[IS_XY ? XY_TAB : 1];  // XY: cos/sin(k 2pi/128)
+    // clock: the paper's tables, cos (= the pair energy rule) and sin of 2 pi k / q
+    __shared__ double s_trig[IS_CK ? 2 * CLOCK_QMAX : 1];
+    __shared__ uint32_t s_axis[2];  // clock: this sweep's and the previous sweep's mirror axis
 
     const int2 tm = tmap[tile_slot()];
     if (tm.x < 0) return;
@@ -282,6 +346,13 @@ k_bond(const InstDesc *__restrict__ descs,
         s_phi[2] = sp;
         s_phi[3] = from_labels ? xy_phi(d, n - 1u) : 0.0;
     }
+    if (IS_CK) {
+        for (int i = tid; i < 2 * d.q; i += NT) s_trig[i] = d.clock_trig[i];
+        if (tid == 0) {
+            s_axis[0] = clock_axis(d, n);
+            s_axis[1] = from_labels ? clock_axis(d, n - 1u) : 0u;
+        }
+    }
     if (MODEL == POTTS && meas)
         for (int q = tid; q < d.q; q += NT) s_hist[q] = 0;
     for (int r = tid; r < ROWS; r += NT) s_rowg[r] = gat((uint32_t)x0, r % TY, r / TY);
@@ -306,9 +377,11 @@ k_bond(const InstDesc *__restrict__ descs,
             s_dm[r] = ((unsigned long long)hi << 32) | lo;
         }
     }
-    if (IS_XY || (MODEL == POTTS && meas)) __syncthreads();
+    if (VEC || (MODEL == POTTS && meas)) __syncthreads();
     const double phi = IS_XY ? s_phi[0] : 0.0, cphi = IS_XY ? s_phi[1] : 0.0, sphi = IS_XY ? s_phi[2] : 0.0;
     const double phi_prev = IS_XY ? s_phi[3] : 0.0;
+    const uint32_t axis = IS_CK ? s_axis[0] : 0u, axis_prev = IS_CK ? s_axis[1] : 0u;
+    const uint32_t uq = (uint32_t)d.q;
 
     // ---- states of the wave's rows, their +y/+z rows and the +x halo column --
     // Ising / Potts keep the states; XY keeps (cos theta, sin theta) in FP64.
@@ -317,6 +390,18 @@ k_bond(const InstDesc *__restrict__ descs,
     // XY: the angles entering the previous sweep of the chain, and this sweep's
     const GLOBAL float *th_prev = IS_XY ? (const GLOBAL float *)(((n - 1u) & 1u) ? d.theta_w[1] : d.theta_w[0]) : nullptr;
     GLOBAL float *th_cur = IS_XY ? (GLOBAL float *)((n & 1u) ? d.theta_w[1] : d.theta_w[0]) : nullptr;
+    // clock: the same for the state indices
+    const GLOBAL uint16_t *ck_prev =
+        IS_CK ? (const GLOBAL uint16_t *)(((n - 1u) & 1u) ? d.theta_w[1] : d.theta_w[0]) : nullptr;
+    GLOBAL uint16_t *ck_cur = IS_CK ? (GLOBAL uint16_t *)((n & 1u) ? d.theta_w[1] : d.theta_w[0]) : nullptr;
+    typedef typename WorkOf<MODEL>::type W;
+    // clock: incoming state index of site g
+    auto clock_in = [&](uint32_t g) -> uint32_t {
+        if (!from_labels) return (uint32_t)((const GLOBAL uint16_t *)d.state)[g];
+        const uint32_t w = root_word(lab_prev, lab_prev[g], d);
+        const uint32_t p = ck_prev[g];
+        return (w & 1u) ? clock_mirror(p, axis_prev, uq) : p;
+    };
     // XY: incoming angle of site g
     auto theta_in = [&](uint32_t g) -> float {
         if (!from_labels) return ((const GLOBAL float *)d.state)[g];
@@ -330,6 +415,9 @@ k_bond(const InstDesc *__restrict__ descs,
             xy_sincos(theta_in(g), s_cs, cv, sv);
             vs = sv;
             return cv;
+        } else if constexpr (IS_CK) {
+            vs = 0;
+            return (V)clock_in(g);
         } else {
             vs = 0;
             if (from_labels) {
@@ -340,7 +428,7 @@ k_bond(const InstDesc *__restrict__ descs,
         }
     };
     // the wavefront's own rows; XY stores the incoming angles for the next sweep
-    auto set_own = [&](int j, uint32_t g, uint32_t dec, float th_old) {
+    auto set_own = [&](int j, uint32_t g, uint32_t dec, W th_old) {
         if constexpr (IS_XY) {
             const float th = from_labels ? ((dec & 1u) ? xy_reflect(th_old, phi_prev) : th_old) : th_old;
             if (full) th_cur[g] = th;
@@ -348,6 +436,11 @@ k_bond(const InstDesc *__restrict__ descs,
             xy_sincos(th, s_cs, cv, sv);
             own[j] = cv;
             ownS[j] = sv;
+        } else if constexpr (IS_CK) {
+            const uint32_t p = from_labels ? ((dec & 1u) ? clock_mirror(th_old, axis_prev, uq) : th_old) : th_old;
+            if (full) ck_cur[g] = (uint16_t)p;
+            own[j] = p;
+            ownS[j] = 0;
         } else {
             own[j] = from_labels ? (V)state_of_decision<MODEL>(dec & 0xffu) : (V)(uint8_t)g_st[g];
             ownS[j] = 0;
@@ -392,15 +485,16 @@ k_bond(const InstDesc *__restrict__ descs,
 #pragma unroll
         for (int h = 0; h < R; h += RH) {
             uint32_t w[RH], cur[RH], val[RH];
-            float tho[RH];
+            W tho[RH];
 #pragma unroll
             for (int i = 0; i < RH; ++i) {
                 w[i] = ROOT_FLAG;
-                tho[i] = 0.0f;
+                tho[i] = 0;
                 if (vc && row_ok(h + i)) {
                     const uint32_t g0 = gin((uint32_t)x0, row_y(h + i), row_z(h + i));
                     w[i] = (lab_prev + g0)[c];
-                    if (IS_XY) tho[i] = (th_prev + g0)[c];
+                    if constexpr (IS_XY) tho[i] = (th_prev + g0)[c];
+                    if constexpr (IS_CK) tho[i] = (ck_prev + g0)[c];
                 }
             }
 #pragma unroll
@@ -450,7 +544,10 @@ k_bond(const InstDesc *__restrict__ descs,
             ownS[j] = 0;
             if (vc && row_ok(j)) {
                 const uint32_t g = gin(gx, row_y(j), row_z(j));
-                set_own(j, g, 0u, IS_XY ? ((const GLOBAL float *)d.state)[g] : 0.0f);
+                W th0 = 0;
+                if constexpr (IS_XY) th0 = ((const GLOBAL float *)d.state)[g];
+                if constexpr (IS_CK) th0 = ((const GLOBAL uint16_t *)d.state)[g];
+                set_own(j, g, 0u, th0);
             }
         }
     }
@@ -474,11 +571,13 @@ k_bond(const InstDesc *__restrict__ descs,
             return;
         }
         uint32_t w[4], val[4];
-        float th[4];
+        W th[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             w[i] = use[i] ? lab_prev[g[i]] : ROOT_FLAG;
-            th[i] = (IS_XY && use[i]) ? th_prev[g[i]] : 0.0f;
+            th[i] = 0;
+            if constexpr (IS_XY) th[i] = use[i] ? th_prev[g[i]] : 0.0f;
+            if constexpr (IS_CK) th[i] = use[i] ? (uint32_t)ck_prev[g[i]] : 0u;
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) val[i] = (w[i] & ROOT_FLAG) ? w[i] : lab_prev[w[i]];
@@ -509,6 +608,8 @@ k_bond(const InstDesc *__restrict__ descs,
             if (!use[i]) continue;
             if constexpr (IS_XY) {
                 xy_sincos((val[i] & 1u) ? xy_reflect(th[i], phi_prev) : th[i], s_cs, v[i], vs[i]);
+            } else if constexpr (IS_CK) {
+                v[i] = (val[i] & 1u) ? clock_mirror(th[i], axis_prev, uq) : th[i];
             } else {
                 v[i] = (V)state_of_decision<MODEL>(val[i] & 0xffu);
             }
@@ -518,11 +619,11 @@ k_bond(const InstDesc *__restrict__ descs,
     // Ising / Potts: lane g < NG holds that column's four rows of group g
     V hx = 0, hxS = 0;
     uint32_t hxg = 0;
-    if (IS_XY && c < R) {
+    if (VEC && c < R) {
         const int ly = DIM == 2 ? r0 + c : c % TY, lz = DIM == 2 ? 0 : r0 / TY + c / TY;
         if (ly < ey && lz < ez) hx = value_at(gin(gxr, ly, lz), hxS);
     }
-    if (!IS_XY && c < NG) {
+    if (!VEC && c < NG) {
         uint32_t hg[4];
         bool hu[4];
         V hv[4], hvs[4];
@@ -563,9 +664,9 @@ k_bond(const InstDesc *__restrict__ descs,
     // (fewer wavefronts per SIMD) do not: there the barrier cost more than
     // the loads it saved.
     constexpr int HG = (DIM == 2) ? 1 : TY / 4;  // row groups handed over
-    constexpr bool HAND = !IS_XY && DIM == 3;
+    constexpr bool HAND = !VEC && DIM == 3;
     static_assert(HG <= NG, "the handed-over rows fit the receiving wavefront's nodes");
-    if constexpr (!IS_XY) {
+    if constexpr (!VEC) {
 #pragma unroll
         for (int gi = 0; gi < NG; ++gi)
             P[gi] = own[4 * gi] | (own[4 * gi + 1] << 8) | (own[4 * gi + 2] << 16) | (own[4 * gi + 3] << 24);
@@ -595,7 +696,7 @@ k_bond(const InstDesc *__restrict__ descs,
         const bool zhi = (gyf & 4u) != 0;
         const uint32_t zwa = zhi ? zw.z : zw.x, zwb = zhi ? zw.w : zw.y;
         const uint32_t zs[4] = {zwa >> 16, zwa & 0xffffu, zwb >> 16, zwb & 0xffffu};
-        if constexpr (!IS_XY) {
+        if constexpr (!VEC) {
             // rows of the group inside the lattice, bit 7 of their byte
             uint32_t vb = 0;
 #pragma unroll
@@ -743,12 +844,36 @@ k_bond(const InstDesc *__restrict__ descs,
                         znS = zbufS[m];
                     }
                 }
+                const uint32_t g = gin(gx, ly, lz);
+                if constexpr (IS_CK) {
+                    // clock: integer states; measurement from the paper's tables
+                    uint32_t rt = from_right((uint32_t)own[j]);
+                    if (c == ex - 1) rt = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)hx, j);
+                    const uint32_t pi = own[j];
+                    if (meas && vc) {
+                        sx_acc += s_trig[pi];
+                        sy_acc += s_trig[uq + pi];
+                        // pair energy -cos(2 pi (p_i - p_j) / q) = -rule[(p_i - p_j) mod q]
+                        e_acc -= s_trig[(pi + uq - rt) % uq];
+                        e_acc -= s_trig[(pi + uq - (uint32_t)up) % uq];
+                        if (DIM == 3) e_acc -= s_trig[(pi + uq - (uint32_t)zn) % uq];
+                    }
+                    if (full && vc) {
+                        const uint32_t px = ws[m] >> 16, py = ws[m] & 0xffffu, pz = zs[m];
+                        const uint32_t onx = clock_bond(pi, rt, axis, d, px, g, 0, key0, key1, rep, n, DIM);
+                        const uint32_t ony = clock_bond(pi, up, axis, d, py, g, 1, key0, key1, rep, n, DIM);
+                        const uint32_t onz = DIM == 3 ? clock_bond(pi, zn, axis, d, pz, g, 2, key0, key1, rep, n, DIM) : 0u;
+                        bxg[gi] |= onx << (8 * m + 7);
+                        byg[gi] |= ony << (8 * m + 7);
+                        bzg[gi] |= onz << (8 * m + 7);
+                    }
+                    continue;
+                }
                 V rt = from_right_d(own[j]), rtS = from_right_d(ownS[j]);
                 if (c == ex - 1) {
                     rt = readlane_d(hx, j);
                     rtS = readlane_d(hxS, j);
                 }
-                const uint32_t g = gin(gx, ly, lz);
                 if (meas && vc) {
                     sx_acc += own[j];
                     sy_acc += ownS[j];
@@ -800,7 +925,7 @@ k_bond(const InstDesc *__restrict__ descs,
         // merge's reduction of one tile's partials gives the same values)
         const bool own_rec = full && d.ntiles == 1 && d.rec_row0 >= 0 && d.rec_row0 + (int64_t)k < d.rec_cap;
         GLOBAL int64_t *rec = (GLOBAL int64_t *)d.rec + (own_rec ? (d.rec_row0 + (int64_t)k) * d.nslots : 0);
-        if (IS_XY) {
+        if (VEC) {
             const double a = wave_sum_d(e_acc), b = wave_sum_d(sx_acc), cc = wave_sum_d(sy_acc);
             if (c == 0) {
                 s_red[wv][0] = a;
@@ -825,7 +950,7 @@ k_bond(const InstDesc *__restrict__ descs,
             double v[3] = {0.0, 0.0, 0.0};
             for (int w = 0; w < NW; ++w)
                 for (int q = 0; q < 3; ++q) v[q] += s_red[w][q];
-            if (IS_XY) {
+            if (VEC) {
                 for (int q = 0; q < 3; ++q) part[q] = __double_as_longlong(v[q]);
                 if (own_rec)
                     for (int q = 0; q < 3; ++q) rec[q] = __double_as_longlong(v[q]);
@@ -1036,6 +1161,7 @@ __global__ void __launch_bounds__(64 * NW, (MODEL == XY) ? 4 : 8) k_flip(const I
     constexpr int R = ROWS / NW;
     static_assert(TX == 64 && ROWS % NW == 0, "lane = column, whole rows per wavefront");
     __shared__ double s_phi;
+    __shared__ uint32_t s_axis;
     const int2 tm = tmap[tile_slot()];
     if (tm.x < 0) return;
     const InstDesc d = descs[tm.x];
@@ -1063,6 +1189,10 @@ __global__ void __launch_bounds__(64 * NW, (MODEL == XY) ? 4 : 8) k_flip(const I
         if (tid == 0) s_phi = xy_phi(d, n);
         __syncthreads();
     }
+    if (MODEL == CLOCK) {
+        if (tid == 0) s_axis = clock_axis(d, n);
+        __syncthreads();
+    }
     GLOBAL uint32_t *g_label = (GLOBAL uint32_t *)labels_of(d, n);
     auto row_ok = [&](int j) -> bool {
         const int rr = r0 + j;
@@ -1077,6 +1207,7 @@ __global__ void __launch_bounds__(64 * NW, (MODEL == XY) ? 4 : 8) k_flip(const I
     // wavefront on (registers for 8 wavefronts per SIMD)
     constexpr int RH = (R >= 16) ? R / 2 : R;
     const double phi = (MODEL == XY) ? s_phi : 0.0;
+    const uint32_t axis = (MODEL == CLOCK) ? s_axis : 0u;
 #pragma unroll 1
     for (int h = 0; h < R; h += RH) {
         uint32_t w[RH], cur[RH], val[RH];
@@ -1127,6 +1258,10 @@ __global__ void __launch_bounds__(64 * NW, (MODEL == XY) ? 4 : 8) k_flip(const I
                 ((GLOBAL int8_t *)d.state)[g] = dec ? (int8_t)-1 : (int8_t)1;
             } else if (MODEL == POTTS) {
                 ((GLOBAL uint8_t *)d.state)[g] = (uint8_t)dec;
+            } else if (MODEL == CLOCK) {
+                // the state that entered the sweep, mirrored or kept
+                const uint32_t p = ((const GLOBAL uint16_t *)((n & 1u) ? d.theta_w[1] : d.theta_w[0]))[g];
+                ((GLOBAL uint16_t *)d.state)[g] = (uint16_t)(dec ? clock_mirror(p, axis, (uint32_t)d.q) : p);
             } else {
                 // the angle that entered the sweep, mirrored or kept
                 const float t = ((const GLOBAL float *)((n & 1u) ? d.theta_w[1] : d.theta_w[0]))[g];
@@ -1150,10 +1285,10 @@ static hipError_t bond_dispatch(int v, const InstDesc *dd, const int2 *tm, int n
                                tm + nf, k, mode);                                                              \
         return hipGetLastError();                                                                              \
     }
-    if constexpr (MODEL != XY && DIM == 2) { SW_VARIANTS_ISING2 }
-    if constexpr (MODEL != XY && DIM == 3) { SW_VARIANTS_ISING3 }
-    if constexpr (MODEL == XY && DIM == 2) { SW_VARIANTS_XY2 }
-    if constexpr (MODEL == XY && DIM == 3) { SW_VARIANTS_XY3 }
+    if constexpr (MODEL < XY && DIM == 2) { SW_VARIANTS_ISING2 }
+    if constexpr (MODEL < XY && DIM == 3) { SW_VARIANTS_ISING3 }
+    if constexpr (MODEL >= XY && DIM == 2) { SW_VARIANTS_XY2 }
+    if constexpr (MODEL >= XY && DIM == 3) { SW_VARIANTS_XY3 }
 #undef X
     return hipErrorInvalidValue;
 }
@@ -1166,10 +1301,10 @@ static hipError_t flip_dispatch(int v, const InstDesc *dd, const int2 *tm, int n
         hipLaunchKernelGGL((k_flip<MODEL, DIM, a, b, c, w>), dim3(nt), dim3(64 * w), 0, s, dd, tm, k); \
         return hipGetLastError();                                                                    \
     }
-    if constexpr (MODEL != XY && DIM == 2) { SW_VARIANTS_ISING2 }
-    if constexpr (MODEL != XY && DIM == 3) { SW_VARIANTS_ISING3 }
-    if constexpr (MODEL == XY && DIM == 2) { SW_VARIANTS_XY2 }
-    if constexpr (MODEL == XY && DIM == 3) { SW_VARIANTS_XY3 }
+    if constexpr (MODEL < XY && DIM == 2) { SW_VARIANTS_ISING2 }
+    if constexpr (MODEL < XY && DIM == 3) { SW_VARIANTS_ISING3 }
+    if constexpr (MODEL >= XY && DIM == 2) { SW_VARIANTS_XY2 }
+    if constexpr (MODEL >= XY && DIM == 3) { SW_VARIANTS_XY3 }
 #undef X
     return hipErrorInvalidValue;
 }

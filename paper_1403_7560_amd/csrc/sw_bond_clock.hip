@@ -1,0 +1,19 @@
+// sw_bond_clock.hip -- CLOCK instantiations of the bond and flip kernels.
+#include "sw_bond.h"
+
+namespace swmc {
+
+hipError_t launch_bond_clock(int dim, int v, const InstDesc *dd, const int2 *tm, int nt, int nf, uint32_t k,
+                          int mode, hipStream_t s)
+{
+    return dim == 2 ? bond_dispatch<CLOCK, 2>(v, dd, tm, nt, nf, k, mode, s)
+                    : bond_dispatch<CLOCK, 3>(v, dd, tm, nt, nf, k, mode, s);
+}
+
+hipError_t launch_flip_clock(int dim, int v, const InstDesc *dd, const int2 *tm, int nt, uint32_t k,
+                          hipStream_t s)
+{
+    return dim == 2 ? flip_dispatch<CLOCK, 2>(v, dd, tm, nt, k, s) : flip_dispatch<CLOCK, 3>(v, dd, tm, nt, k, s);
+}
+
+}  // namespace swmc

@@ -65,6 +65,7 @@ template <int MODEL> struct StateOf;
 template <> struct StateOf<ISING> { typedef int8_t type; };
 template <> struct StateOf<POTTS> { typedef uint8_t type; };
 template <> struct StateOf<XY> { typedef float type; };
+template <> struct StateOf<CLOCK> { typedef uint16_t type; };
 
 __device__ __forceinline__ int wave_sum_i(int v)
 {

@@ -40,7 +40,10 @@ int fail(int code, const std::string &msg)
             return fail(SW_E_DEVICE, std::string(#x) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
-size_t state_bytes(int model) { return model == XY ? 4 : 1; }
+const double PI_D_HOST = 3.141592653589793238462643383279;
+const double TWO_PI_D_HOST = 6.283185307179586476925286766559;
+
+size_t state_bytes(int model) { return model == XY ? 4 : (model == CLOCK ? 2 : 1); }
 
 double now_s()
 {
@@ -58,7 +61,7 @@ uint64_t bond_threshold(int model, double beta)
 
 int validate(int model, int dim, int L, int q, double beta)
 {
-    if (model < 0 || model > 2) return fail(SW_E_INVALID, "model must be 0 (Ising), 1 (Potts) or 2 (XY)");
+    if (model < 0 || model > 3) return fail(SW_E_INVALID, "model must be 0 (Ising), 1 (Potts), 2 (XY) or 3 (clock)");
     if (dim != 2 && dim != 3) return fail(SW_E_INVALID, "dim must be 2 or 3");
     if (L < 3) return fail(SW_E_INVALID, "L must be >= 3");
     double n = 1.0;
@@ -66,6 +69,8 @@ int validate(int model, int dim, int L, int q, double beta)
     if (n > 2147483647.0) return fail(SW_E_INVALID, "L^dim must be < 2^31");
     if (model == POTTS && (q < 2 || q > 256)) return fail(SW_E_INVALID, "Potts needs 2 <= q <= 256");
     if (model == ISING && !(q == 0 || q == 2)) return fail(SW_E_INVALID, "Ising takes q = 2 (or 0)");
+    if (model == CLOCK && (q < 2 || q > CLOCK_QMAX || (q & 1)))
+        return fail(SW_E_INVALID, "the clock model needs an even q in [2, 512]");
     if (!(beta >= 0.0) || !std::isfinite(beta)) return fail(SW_E_INVALID, "beta must be finite and >= 0");
     return SW_OK;
 }
@@ -127,6 +132,8 @@ struct Lattice {
     uint32_t *rbuf = nullptr;      // Hawick's R, N words
     uint32_t *ctl = nullptr;       // barrier and convergence words of one launch
     int ctl_words = 0;
+    uint32_t *clock_thr = nullptr;  // clock model: bond thresholds of projection-index pairs
+    double *clock_trig = nullptr;   // clock model: cos, sin of 2 pi k / q
     void *state = nullptr;
     uint32_t *label = nullptr;   // label words of even sweeps
     uint32_t *label2 = nullptr;  // label words of odd sweeps
@@ -141,7 +148,7 @@ struct Lattice {
     int2 *d_tmap = nullptr;      // tile map for solo sweeps
     hipStream_t stream = nullptr;
     // per-kernel event timing
-    int profiling = 0;  // 1: events around k_bond; 2: also around k_merge
+    int profiling = 0;  // 1: events around k_bond; 2: also around the global phase and the flip
     // events bracket the launches of every PROFILE_EVERY-th sweep only: an
     // event pair around every launch would slow the sweep it measures
     static constexpr int64_t PROFILE_EVERY = 16;
@@ -168,7 +175,7 @@ struct Lattice {
     void release()
     {
         void *ptrs[] = {state, label, label2, theta_w[0], theta_w[1], bond, face, part, rec, d_solo, d_tmap, err,
-                        edges, ecount, rbuf, ctl};
+                        edges, ecount, rbuf, ctl, clock_thr, clock_trig};
         for (void *p : ptrs)
             if (p) (void)hipFree(p);
         state = nullptr;
@@ -186,6 +193,8 @@ struct Lattice {
         ecount = nullptr;
         rbuf = nullptr;
         ctl = nullptr;
+        clock_thr = nullptr;
+        clock_trig = nullptr;
     }
 
     static int64_t footprint(int model, int dim, int L, int q, int variant)
@@ -201,8 +210,9 @@ struct Lattice {
         for (int mu = 0; mu < dim; ++mu)
             if (t[mu] > 1) face += nt * 2 * (T / ext[mu]) * 4;
         const int ns = slots_for(model, q);
-        return N * (int64_t)state_bytes(model) * (model == XY ? 3 : 1) + 2 * N * 4 + N + face + nt * ns * 8 +
-               1025 * ns * 8 +
+        const int64_t tables = model == CLOCK ? (int64_t)(q / 2 + 1) * (q / 2 + 1) * 4 + 2 * q * 8 : 0;
+        return N * (int64_t)state_bytes(model) * (model >= XY ? 3 : 1) + 2 * N * 4 + N + face + nt * ns * 8 +
+               1025 * ns * 8 + tables + 256 +
                (int64_t)sizeof(InstDesc) + nt * 8;
     }
 
@@ -218,7 +228,7 @@ struct Lattice {
         d.ntiles = ntiles;
         d.nslots = nslots;
         d.N = N;
-        d.thr = (model == XY) ? 0 : bond_threshold(model, beta);
+        d.thr = (model >= XY) ? 0 : bond_threshold(model, beta);
         d.thr_hi = (uint32_t)(d.thr >> 16);
         d.thr_lo = (uint32_t)(d.thr & 0xffffu);
         d.two_beta = 2.0 * beta;
@@ -253,7 +263,41 @@ struct Lattice {
         d.edge_cap = edge_cap;
         d.rbuf = rbuf;
         d.lstats = (uint64_t *)((char *)err + 64);
+        d.clock_thr = clock_thr;
+        d.clock_trig = clock_trig;
         return d;
+    }
+
+    // Clock model tables (per q and beta): the integer bond threshold of two
+    // projection indices m1, m2 in [0, q/2] -- floor(p 2^32), capped at
+    // 2^32 - 1, with p = -expm1(-(2 beta)(cos(pi m1/q) cos(pi m2/q))); the
+    // index q/2 (a spin perpendicular to the axis) never bonds -- and the
+    // paper's pair-energy table rule[k] = cos(2 pi k/q) with sin(2 pi k/q)
+    // for the magnetisation.
+    int build_clock_tables()
+    {
+        const int H = q / 2 + 1;
+        std::vector<double> c(H);
+        for (int m = 0; m < H; ++m) c[m] = std::cos((PI_D_HOST * (double)m) / (double)q);
+        std::vector<uint32_t> thr((size_t)H * H, 0u);
+        for (int a = 0; a < H - 1; ++a)
+            for (int b = 0; b < H - 1; ++b) {
+                const double x = (2.0 * beta) * (c[a] * c[b]);
+                const double p = -std::expm1(-x);
+                if (!(p > 0.0)) continue;
+                const double t = std::floor(std::ldexp(p, 32));
+                thr[(size_t)a * H + b] = t >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)t;
+            }
+        std::vector<double> trig(2 * (size_t)q);
+        for (int k = 0; k < q; ++k) {
+            trig[k] = std::cos((TWO_PI_D_HOST * (double)k) / (double)q);
+            trig[q + k] = std::sin((TWO_PI_D_HOST * (double)k) / (double)q);
+        }
+        if (hipMalloc(&clock_thr, thr.size() * 4) != hipSuccess || hipMalloc(&clock_trig, trig.size() * 8) != hipSuccess)
+            return fail(SW_E_NOMEM, "clock table allocation failed");
+        HIPCHK(hipMemcpy(clock_thr, thr.data(), thr.size() * 4, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(clock_trig, trig.data(), trig.size() * 8, hipMemcpyHostToDevice));
+        return SW_OK;
     }
 
     // Select the global labelling phase; the iterative ones get their edge
@@ -334,7 +378,7 @@ struct Lattice {
         model = model_;
         dim = dim_;
         L = L_;
-        q = (model == ISING) ? 2 : (model == XY ? 0 : q_);
+        q = (model == ISING) ? 2 : (model == XY ? 0 : q_);  // Potts and clock keep their q
         beta = beta_;
         seed = seed_;
         rep = rep_;
@@ -360,8 +404,8 @@ struct Lattice {
         if (hipMalloc(&state, (size_t)N * state_bytes(model)) != hipSuccess ||
             hipMalloc(&label, (size_t)N * 4) != hipSuccess || hipMalloc(&label2, (size_t)N * 4) != hipSuccess ||
             hipMalloc(&bond, (size_t)N) != hipSuccess ||
-            (model == XY && (hipMalloc(&theta_w[0], (size_t)N * 4) != hipSuccess ||
-                             hipMalloc(&theta_w[1], (size_t)N * 4) != hipSuccess)) ||
+            (model >= XY && (hipMalloc(&theta_w[0], (size_t)N * state_bytes(model)) != hipSuccess ||
+                             hipMalloc(&theta_w[1], (size_t)N * state_bytes(model)) != hipSuccess)) ||
             hipMalloc(&face, (size_t)std::max<int64_t>(face_total, 1) * 4) != hipSuccess ||
             hipMalloc(&part, (size_t)ntiles * nslots * 8) != hipSuccess ||
             hipMalloc(&d_solo, sizeof(InstDesc)) != hipSuccess ||
@@ -372,6 +416,10 @@ struct Lattice {
         }
         walk_cap = (uint32_t)(N + 1);
         max_iters = 64;
+        if (model == CLOCK) {
+            rc = build_clock_tables();
+            if (rc) return rc;
+        }
         rc = grow_records(1024);
         if (rc) return rc;
         HIPCHK(hipMemsetAsync(err, 0, 256, stream));
@@ -411,9 +459,11 @@ struct Lattice {
             const int64_t first_timed = (PROFILE_EVERY - sweep % PROFILE_EVERY) % PROFILE_EVERY;
             const int64_t ntimed = first_timed < m ? (m - 1 - first_timed) / PROFILE_EVERY + 1 : 0;
             if (profiling) {
-                int rc = ensure_events((size_t)(4 * std::max<int64_t>(ntimed, 1)));
+                // 4 per timed sweep, then the pair around the chain's flip
+                int rc = ensure_events((size_t)(4 * std::max<int64_t>(ntimed, 1) + 2));
                 if (rc) return rc;
             }
+            hipEvent_t *fev = profiling > 1 ? &events[events.size() - 2] : nullptr;
             // each sweep's bond kernel applies the previous sweep's cluster
             // decisions; the chain's last decisions are applied once at the end
             for (int64_t k = 0; k < m; ++k) {
@@ -425,8 +475,16 @@ struct Lattice {
                 HIPCHK(launch_global((uint32_t)k));
                 if (ev && profiling > 1) HIPCHK(hipEventRecord(ev[2], stream));
             }
+            if (fev) HIPCHK(hipEventRecord(fev[0], stream));
             HIPCHK(launch_flip(model, dim, variant, d_solo, d_tmap, ntiles, FLIP_LAST, stream));
+            if (fev) HIPCHK(hipEventRecord(fev[1], stream));
             HIPCHK(hipStreamSynchronize(stream));
+            if (fev) {
+                float ms = 0.f;
+                HIPCHK(hipEventElapsedTime(&ms, fev[0], fev[1]));
+                prof_ms[2] += ms;
+                prof_n[2] += 1;
+            }
             if (profiling) {
                 const int nk = profiling > 1 ? 2 : 1;
                 for (int64_t k = 0; k < ntimed; ++k) {
@@ -483,7 +541,7 @@ struct Lattice {
             const __int128 num = (__int128)q * s2 - (__int128)N * N;
             o.mag2 = (double)num / (double)(q - 1);
             o.mag = std::sqrt(std::max(0.0, o.mag2));
-        } else {
+        } else {  // XY and clock: E, Mx, My as doubles
             double v[3];
             std::memcpy(v, r, sizeof(v));
             o.energy = v[0];
@@ -1029,13 +1087,13 @@ sw_handle sw_create_replica(int model, int dim, int L, int q, double beta, uint6
 
 int sw_tile_count(int model, int dim)
 {
-    if (model < 0 || model > 2 || (dim != 2 && dim != 3)) return fail(SW_E_INVALID, "bad model or dim");
+    if (model < 0 || model > 3 || (dim != 2 && dim != 3)) return fail(SW_E_INVALID, "bad model or dim");
     return num_tile_variants(model, dim);
 }
 
 int sw_tile_shape(int model, int dim, int tile, int *tx, int *ty, int *tz)
 {
-    if (model < 0 || model > 2 || (dim != 2 && dim != 3)) return fail(SW_E_INVALID, "bad model or dim");
+    if (model < 0 || model > 3 || (dim != 2 && dim != 3)) return fail(SW_E_INVALID, "bad model or dim");
     if (tile < 0 || tile >= num_tile_variants(model, dim)) return fail(SW_E_INVALID, "unknown tile shape");
     const TileShape t = tile_shape(model, dim, tile);
     if (tx) *tx = t.tx;
@@ -1252,6 +1310,10 @@ int sw_set_state(sw_handle h, const void *host)
         const uint8_t *s = (const uint8_t *)host;
         for (int64_t i = 0; i < l.N; ++i)
             if (s[i] >= l.q) return fail(SW_E_INVALID, "Potts states must be < q");
+    } else if (l.model == CLOCK) {
+        const uint16_t *s = (const uint16_t *)host;
+        for (int64_t i = 0; i < l.N; ++i)
+            if (s[i] >= l.q) return fail(SW_E_INVALID, "clock states must be < q");
     } else {
         const float *s = (const float *)host;
         const float top = (float)6.283185307179586476925286766559;
@@ -1373,7 +1435,7 @@ void sw_batch_destroy(sw_batch b) { delete b; }
 int64_t sw_footprint(int model, int dim, int L, int q)
 {
     if (validate(model, dim, L, (model == ISING) ? 2 : q, 0.0)) return SW_E_INVALID;
-    return Lattice::footprint(model, dim, L, (model == ISING) ? 2 : (model == XY ? 0 : q), 0);
+    return Lattice::footprint(model, dim, L, (model == ISING) ? 2 : (model == XY ? 0 : q), 0);  // Potts, clock: q
 }
 
 sw_server sw_server_create(int64_t budget, int max_active, int chunk)

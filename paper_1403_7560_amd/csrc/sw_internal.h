@@ -6,7 +6,9 @@
 
 namespace swmc {
 
-enum { ISING = 0, POTTS = 1, XY = 2 };
+enum { ISING = 0, POTTS = 1, XY = 2, CLOCK = 3 };
+// Clock model: the largest q (the paper's shared-memory table limit).
+constexpr int CLOCK_QMAX = 512;
 enum { TAG_BOND = 0, TAG_BOND_Z = 1, TAG_BOND_TIE = 2, TAG_CLUSTER = 3, TAG_GLOBAL = 4,
        TAG_INIT = 5 };
 
@@ -63,6 +65,10 @@ struct InstDesc {
     int32_t edge_cap;
     uint32_t *rbuf;
     uint64_t *lstats;
+    // Clock model: integer bond thresholds of two projection indices,
+    // [(q/2 + 1)^2], and cos, sin of 2 pi k / q, k < q ([2q]).
+    uint32_t *clock_thr;
+    double *clock_trig;
 };
 
 // Bits of a lattice's device error word.
@@ -106,6 +112,9 @@ hipError_t launch_bond_xy(int dim, int v, const InstDesc *dd, const int2 *tm, in
 hipError_t launch_flip_ising(int dim, int v, const InstDesc *dd, const int2 *tm, int nt, uint32_t k, hipStream_t s);
 hipError_t launch_flip_potts(int dim, int v, const InstDesc *dd, const int2 *tm, int nt, uint32_t k, hipStream_t s);
 hipError_t launch_flip_xy(int dim, int v, const InstDesc *dd, const int2 *tm, int nt, uint32_t k, hipStream_t s);
+hipError_t launch_bond_clock(int dim, int v, const InstDesc *dd, const int2 *tm, int nt, int nf, uint32_t k,
+                             int mode, hipStream_t s);
+hipError_t launch_flip_clock(int dim, int v, const InstDesc *dd, const int2 *tm, int nt, uint32_t k, hipStream_t s);
 
 // The paper's iterative labellers for the global phase (alg 0 Hawick, 1
 // Kalentev; defined in sw_label.hip): one cooperative launch per sweep that

@@ -49,6 +49,8 @@ __global__ void __launch_bounds__(256) k_init(const InstDesc *__restrict__ descs
             ((int8_t *)d.state)[i] = (ws[m] >> 31) ? (int8_t)-1 : (int8_t)1;
         } else if (MODEL == POTTS) {
             ((uint8_t *)d.state)[i] = (uint8_t)(((uint64_t)ws[m] * (uint64_t)d.q) >> 32);
+        } else if (MODEL == CLOCK) {
+            ((uint16_t *)d.state)[i] = (uint16_t)(((uint64_t)ws[m] * (uint64_t)d.q) >> 32);
         } else {
             const double t = ((double)ws[m] * 0x1p-32) * TWO_PI_D;
             float f = (float)t;
@@ -87,7 +89,7 @@ __global__ void __launch_bounds__(256) k_merge(const InstDesc *__restrict__ desc
     const int tid = threadIdx.x;
     // the first workgroups of a lattice also reduce the sweep's measurement
     if (d.measure && d.rec_row0 >= 0 && d.rec_row0 + (int64_t)k < d.rec_cap &&
-        (t < d.nslots || (d.model == XY && t == 0))) {
+        (t < d.nslots || (d.model >= XY && t == 0))) {
         if (d.model == ISING) reduce_partials<ISING>(d, t, d.rec_row0 + (int64_t)k);
         else if (d.model == POTTS) reduce_partials<POTTS>(d, t, d.rec_row0 + (int64_t)k);
         else reduce_partials<XY>(d, t, d.rec_row0 + (int64_t)k);
@@ -229,10 +231,10 @@ int num_tile_variants(int model, int dim)
 {
     int n = 0;
 #define X(i, a, b, c, w) ++n;
-    if (model != XY && dim == 2) { SW_VARIANTS_ISING2 }
-    if (model != XY && dim == 3) { SW_VARIANTS_ISING3 }
-    if (model == XY && dim == 2) { SW_VARIANTS_XY2 }
-    if (model == XY && dim == 3) { SW_VARIANTS_XY3 }
+    if (model < XY && dim == 2) { SW_VARIANTS_ISING2 }
+    if (model < XY && dim == 3) { SW_VARIANTS_ISING3 }
+    if (model >= XY && dim == 2) { SW_VARIANTS_XY2 }
+    if (model >= XY && dim == 3) { SW_VARIANTS_XY3 }
 #undef X
     return n;
 }
@@ -241,10 +243,10 @@ TileShape tile_shape(int model, int dim, int v)
 {
 #define X(i, a, b, c, w) \
     if (v == i) return TileShape{a, b, c};
-    if (model != XY && dim == 2) { SW_VARIANTS_ISING2 }
-    if (model != XY && dim == 3) { SW_VARIANTS_ISING3 }
-    if (model == XY && dim == 2) { SW_VARIANTS_XY2 }
-    if (model == XY && dim == 3) { SW_VARIANTS_XY3 }
+    if (model < XY && dim == 2) { SW_VARIANTS_ISING2 }
+    if (model < XY && dim == 3) { SW_VARIANTS_ISING3 }
+    if (model >= XY && dim == 2) { SW_VARIANTS_XY2 }
+    if (model >= XY && dim == 3) { SW_VARIANTS_XY3 }
 #undef X
     return TileShape{0, 0, 0};
 }
@@ -256,7 +258,7 @@ bool tile_interior(int dim, int L, const TileShape &ts, int t)
     return (tx + 1) * ts.tx <= L && (ty + 1) * ts.ty <= L && (dim == 2 || (tz + 1) * ts.tz <= L);
 }
 
-int slots_for(int model, int q) { return model == ISING ? 2 : (model == POTTS ? 1 + q : 3); }
+int slots_for(int model, int q) { return model == ISING ? 2 : (model == POTTS ? 1 + q : 3); }  // XY, clock: E, Mx, My
 
 hipError_t launch_init(const InstDesc *d_desc, int inst, const InstDesc &h, hipStream_t s)
 {
@@ -264,7 +266,8 @@ hipError_t launch_init(const InstDesc *d_desc, int inst, const InstDesc &h, hipS
     const unsigned grid = (unsigned)((blocks4 + 255) / 256);
     if (h.model == ISING) hipLaunchKernelGGL(k_init<ISING>, dim3(grid), dim3(256), 0, s, d_desc, inst);
     else if (h.model == POTTS) hipLaunchKernelGGL(k_init<POTTS>, dim3(grid), dim3(256), 0, s, d_desc, inst);
-    else hipLaunchKernelGGL(k_init<XY>, dim3(grid), dim3(256), 0, s, d_desc, inst);
+    else if (h.model == XY) hipLaunchKernelGGL(k_init<XY>, dim3(grid), dim3(256), 0, s, d_desc, inst);
+    else hipLaunchKernelGGL(k_init<CLOCK>, dim3(grid), dim3(256), 0, s, d_desc, inst);
     return hipGetLastError();
 }
 
@@ -278,10 +281,10 @@ static hipError_t merge_dispatch(int v, const InstDesc *dd, const int2 *tm, int 
         hipLaunchKernelGGL((k_merge<DIM, E>), dim3(nt), dim3(256), 0, s, dd, tm, k);                      \
         return hipGetLastError();                                                                          \
     }
-    if constexpr (MODEL != XY && DIM == 2) { SW_VARIANTS_ISING2 }
-    if constexpr (MODEL != XY && DIM == 3) { SW_VARIANTS_ISING3 }
-    if constexpr (MODEL == XY && DIM == 2) { SW_VARIANTS_XY2 }
-    if constexpr (MODEL == XY && DIM == 3) { SW_VARIANTS_XY3 }
+    if constexpr (MODEL < XY && DIM == 2) { SW_VARIANTS_ISING2 }
+    if constexpr (MODEL < XY && DIM == 3) { SW_VARIANTS_ISING3 }
+    if constexpr (MODEL >= XY && DIM == 2) { SW_VARIANTS_XY2 }
+    if constexpr (MODEL >= XY && DIM == 3) { SW_VARIANTS_XY3 }
 #undef X
     return hipErrorInvalidValue;
 }
@@ -290,7 +293,7 @@ hipError_t launch_merge(int dim, int model, int v, const InstDesc *dd, const int
                         hipStream_t s)
 {
     if (nt <= 0) return hipSuccess;
-    if (model == XY) return dim == 2 ? merge_dispatch<XY, 2>(v, dd, tm, nt, k, s) : merge_dispatch<XY, 3>(v, dd, tm, nt, k, s);
+    if (model >= XY) return dim == 2 ? merge_dispatch<XY, 2>(v, dd, tm, nt, k, s) : merge_dispatch<XY, 3>(v, dd, tm, nt, k, s);
     return dim == 2 ? merge_dispatch<ISING, 2>(v, dd, tm, nt, k, s) : merge_dispatch<ISING, 3>(v, dd, tm, nt, k, s);
 }
 
@@ -310,7 +313,8 @@ hipError_t launch_bond(int model, int dim, int v, const InstDesc *dd, const int2
     if (nf < 0 || nf > nt) return hipErrorInvalidValue;
     if (model == ISING) return launch_bond_ising(dim, v, dd, tm, nt, nf, k, mode, s);
     if (model == POTTS) return launch_bond_potts(dim, v, dd, tm, nt, nf, k, mode, s);
-    return launch_bond_xy(dim, v, dd, tm, nt, nf, k, mode, s);
+    if (model == XY) return launch_bond_xy(dim, v, dd, tm, nt, nf, k, mode, s);
+    return launch_bond_clock(dim, v, dd, tm, nt, nf, k, mode, s);
 }
 
 hipError_t launch_flip(int model, int dim, int v, const InstDesc *dd, const int2 *tm, int nt, uint32_t k,
@@ -319,7 +323,8 @@ hipError_t launch_flip(int model, int dim, int v, const InstDesc *dd, const int2
     if (nt <= 0) return hipSuccess;
     if (model == ISING) return launch_flip_ising(dim, v, dd, tm, nt, k, s);
     if (model == POTTS) return launch_flip_potts(dim, v, dd, tm, nt, k, s);
-    return launch_flip_xy(dim, v, dd, tm, nt, k, s);
+    if (model == XY) return launch_flip_xy(dim, v, dd, tm, nt, k, s);
+    return launch_flip_clock(dim, v, dd, tm, nt, k, s);
 }
 
 hipError_t launch_canon(const InstDesc *dd, int inst, int64_t N, int32_t *out, hipStream_t s)

@@ -106,7 +106,7 @@ __global__ void __launch_bounds__(256) k_label_iter(const InstDesc *__restrict__
         const int t = tm.y;
         // the first workgroups of a lattice also reduce the sweep's measurement
         if (d.measure && d.rec_row0 >= 0 && d.rec_row0 + (int64_t)k < d.rec_cap &&
-            (t < d.nslots || (d.model == XY && t == 0))) {
+            (t < d.nslots || (d.model >= XY && t == 0))) {
             if (d.model == ISING) reduce_partials<ISING>(d, t, d.rec_row0 + (int64_t)k);
             else if (d.model == POTTS) reduce_partials<POTTS>(d, t, d.rec_row0 + (int64_t)k);
             else reduce_partials<XY>(d, t, d.rec_row0 + (int64_t)k);
@@ -340,10 +340,10 @@ static hipError_t label_dispatch(int v, int alg, const InstDesc *dd, const int2 
         return alg == 0 ? launch_iter<DIM, 0, E>(dd, tm, nt, k, ctl, cap, s)                       \
                         : launch_iter<DIM, 1, E>(dd, tm, nt, k, ctl, cap, s);                      \
     }
-    if constexpr (MODEL != XY && DIM == 2) { SW_VARIANTS_ISING2 }
-    if constexpr (MODEL != XY && DIM == 3) { SW_VARIANTS_ISING3 }
-    if constexpr (MODEL == XY && DIM == 2) { SW_VARIANTS_XY2 }
-    if constexpr (MODEL == XY && DIM == 3) { SW_VARIANTS_XY3 }
+    if constexpr (MODEL < XY && DIM == 2) { SW_VARIANTS_ISING2 }
+    if constexpr (MODEL < XY && DIM == 3) { SW_VARIANTS_ISING3 }
+    if constexpr (MODEL >= XY && DIM == 2) { SW_VARIANTS_XY2 }
+    if constexpr (MODEL >= XY && DIM == 3) { SW_VARIANTS_XY3 }
 #undef X
     return hipErrorInvalidValue;
 }
@@ -353,7 +353,7 @@ hipError_t launch_label_iter(int dim, int model, int variant, int alg, const Ins
 {
     if (nt <= 0) return hipSuccess;
     if ((alg != 0 && alg != 1) || cap < 1) return hipErrorInvalidValue;
-    if (model == XY)
+    if (model >= XY)
         return dim == 2 ? label_dispatch<XY, 2>(variant, alg, dd, tm, nt, k, ctl, cap, s)
                         : label_dispatch<XY, 3>(variant, alg, dd, tm, nt, k, ctl, cap, s);
     return dim == 2 ? label_dispatch<ISING, 2>(variant, alg, dd, tm, nt, k, ctl, cap, s)

@@ -9,11 +9,12 @@ import math
 
 import numpy as np
 
-ISING, POTTS, XY = 0, 1, 2
+ISING, POTTS, XY, CLOCK = 0, 1, 2, 3
 
 TC_ISING_2D = 2.0 / math.log(1.0 + math.sqrt(2.0))  # Onsager
 TC_ISING_3D = 4.5115                                 # paper, Sec. 3 (Table 1 temperature)
 TC_XY_3D = 2.2019                                    # paper, Sec. 3 (near its Tc estimate)
+TC_CLOCK512_3D = 2.20175                             # paper, Sec. 3 (Table 2 temperature)
 
 
 def tc_potts_2d(q):
@@ -28,6 +29,8 @@ def random_state(model, dim, L, q=2, seed=0):
         return np.where(rng.random(N) < 0.5, -1, 1).astype(np.int8)
     if model == POTTS:
         return rng.integers(0, q, N).astype(np.uint8)
+    if model == CLOCK:
+        return rng.integers(0, q, N).astype(np.uint16)
     th = (rng.random(N) * 2 * math.pi).astype(np.float32)
     th[th >= np.float32(2 * math.pi)] = 0.0
     return th
@@ -48,6 +51,8 @@ def ordered_state(model, dim, L, q=2, seed=0, disorder=0.05):
         return np.where(flip, hot, 1).astype(np.int8)
     if model == POTTS:
         return np.where(flip, hot, 0).astype(np.uint8)
+    if model == CLOCK:
+        return np.where(flip, hot, 0).astype(np.uint16)
     th = np.mod(rng.normal(0.0, 0.3, N), 2 * math.pi).astype(np.float32)
     th[th >= np.float32(2 * math.pi)] = 0.0
     return np.where(flip, hot, th).astype(np.float32)
@@ -67,6 +72,8 @@ def workload(name):
         return [dict(lat[0], L=8192)], 2000
     if name == "C3":   # 3D Ising L=256 at T=4.5115
         return [dict(model=ISING, dim=3, L=256, q=2, beta=1 / TC_ISING_3D, seed=4, replica=0)], 2000
+    if name == "CLOCK-512":  # 3D 512-state clock L=256 at T=2.20175 (the paper's Table 2 shape)
+        return [dict(model=CLOCK, dim=3, L=256, q=512, beta=1 / TC_CLOCK512_3D, seed=7, replica=0)], 2000
     if name == "C4":   # 3D XY L=128, 32 replicas over [0.95 Tc, 1.05 Tc]
         lats = []
         for r in range(32):

@@ -90,7 +90,7 @@ def test_bench_refuses_several_gpus():
 
 def test_tile_shapes_are_host_logic():
     import paper_1403_7560_amd as sw
-    for model in (sw.ISING, sw.POTTS, sw.XY):
+    for model in (sw.ISING, sw.POTTS, sw.XY, sw.CLOCK):
         for dim in (2, 3):
             n = sw.tile_count(model, dim)
             assert n >= 1
@@ -102,15 +102,19 @@ def test_tile_shapes_are_host_logic():
                 sw.tile_shape(model, dim, n)
     assert sw.tile_shape(sw.ISING, 2, 0) == (64, 64, 1)
     with pytest.raises(sw.SWError):
-        sw.tile_count(3, 2)
+        sw.tile_count(4, 2)
 
 
 def test_invalid_lattice_arguments_fail_before_the_device():
     """Argument checks (and the default tile rule) run before any HIP call:
     bad arguments raise SW_E_INVALID, with or without a GPU."""
     import paper_1403_7560_amd as sw
-    for args in [(3, 2, 10, 2), (sw.ISING, 4, 10, 2), (sw.ISING, 2, 2, 2), (sw.POTTS, 2, 10, 1),
+    for args in [(4, 2, 10, 2), (sw.ISING, 4, 10, 2), (sw.ISING, 2, 2, 2), (sw.POTTS, 2, 10, 1),
                  (sw.POTTS, 2, 10, 257), (sw.ISING, 3, 1291, 2)]:
+        with pytest.raises(sw.SWError) as e:
+            sw.Lattice(*args, beta=0.4, seed=1)
+        assert e.value.code == -1, args
+    for args in [(sw.CLOCK, 2, 10, 3), (sw.CLOCK, 2, 10, 514), (sw.CLOCK, 2, 10, 0)]:
         with pytest.raises(sw.SWError) as e:
             sw.Lattice(*args, beta=0.4, seed=1)
         assert e.value.code == -1, args
