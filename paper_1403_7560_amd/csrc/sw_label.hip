@@ -32,11 +32,15 @@
 
 namespace swmc {
 
-// ctl words of one launch (zeroed before it):
-//   [0] barrier arrivals, [1] abort (a barrier waited too long),
-//   [2 + it] changed flag of iteration it (it < cap).
-constexpr int CTL_BAR = 0, CTL_ABORT = 1, CTL_CHG = 2;
-constexpr uint32_t BARRIER_SPIN_CAP = 1u << 24;  // about a second of waiting
+// ctl words of one launch (zeroed before it), one 128-byte line apart where
+// many workgroups poll:
+//   [0] barrier arrivals; [32 (1 + x)], x < 8: the barrier generation,
+//   one copy per XCD so that the polling spreads over eight lines;
+//   [288] abort (a barrier waited too long); [320 + it] changed flag of
+//   iteration it (it < cap).
+constexpr int CTL_BAR = 0, CTL_GEN = 32, CTL_ABORT = 288, CTL_CHG = 320;
+// bound of one barrier wait, in ticks of the 100 MHz real-time counter
+constexpr uint64_t BARRIER_WAIT_TICKS = 50000000ull;  // 0.5 s
 
 __device__ __forceinline__ uint32_t aload(const uint32_t *p)
 {
@@ -48,27 +52,41 @@ __device__ __forceinline__ void astore(uint32_t *p, uint32_t v)
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Grid-wide barrier of a cooperative launch: each workgroup's arrival is a
-// release increment, and it waits (acquire) until all have arrived for this
-// epoch.  The wait is bounded: past the cap (or once another workgroup gave
-// up) it sets the abort word and returns false, so every workgroup exits.
+// Grid-wide barrier of a cooperative launch.  Every word another workgroup
+// reads is accessed with device-scope atomics (they go to the coherence
+// point, past the XCD's L2), so the barrier needs no cache maintenance, only
+// that this workgroup's accesses have completed before it arrives: a
+// waitcnt, the workgroup barrier, then one relaxed device-scope increment.
+// The last workgroup to arrive publishes the new generation in eight copies
+// (one per XCD); the others poll their copy with relaxed loads and a sleep.
+// (Acquire loads would invalidate the XCD's L2 on every poll.)  The wait is
+// bounded in time: past BARRIER_WAIT_TICKS, or once another workgroup gave
+// up, it sets the abort word and returns false, and every workgroup exits.
 __device__ bool grid_barrier(uint32_t *ctl, uint32_t &epoch)
 {
     __shared__ int s_ok;
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (threadIdx.x == 0) {
         ++epoch;
-        const uint32_t target = epoch * gridDim.x;
-        __hip_atomic_fetch_add(ctl + CTL_BAR, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t arrived =
+            __hip_atomic_fetch_add(ctl + CTL_BAR, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
         int ok = 1;
-        uint32_t spins = 0;
-        while (__hip_atomic_load(ctl + CTL_BAR, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            if (aload(ctl + CTL_ABORT) != 0u || ++spins > BARRIER_SPIN_CAP) {
-                astore(ctl + CTL_ABORT, 1u);
-                ok = 0;
-                break;
+        if (arrived == epoch * gridDim.x) {
+            for (int x = 0; x < 8; ++x) astore(ctl + CTL_GEN + 32 * x, epoch);
+        } else {
+            uint32_t *gen = ctl + CTL_GEN + 32 * (blockIdx.x & 7u);
+            const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+            uint32_t spins = 0;
+            while (aload(gen) != epoch) {
+                __builtin_amdgcn_s_sleep(8);
+                if ((++spins & 63u) == 0u &&
+                    (aload(ctl + CTL_ABORT) != 0u || __builtin_amdgcn_s_memrealtime() - t0 > BARRIER_WAIT_TICKS)) {
+                    astore(ctl + CTL_ABORT, 1u);
+                    ok = 0;
+                    break;
+                }
             }
-            __builtin_amdgcn_s_sleep(2);
         }
         s_ok = ok;
     }
@@ -227,7 +245,7 @@ __global__ void __launch_bounds__(256) k_label_iter(const InstDesc *__restrict__
                 if ((w & ROOT_FLAG) || w > lo) astore(lab + hi, lo);
             }
         });
-        if (__syncthreads_or(changed) && tid == 0) atomicOr(ctl + CTL_CHG + it, 1u);
+        if (__syncthreads_or(changed) && tid == 0) astore(ctl + CTL_CHG + it, 1u);
         if (!grid_barrier(ctl, epoch)) return;
         if (aload(ctl + CTL_CHG + it) == 0u) {  // the same value in every workgroup
             converged = true;
@@ -322,7 +340,11 @@ static hipError_t launch_iter(const InstDesc *dd, const int2 *tm, int nt, uint32
         if (e != hipSuccess) return e;
         if (per_cu < 1) return hipErrorLaunchOutOfResources;
     }
-    const int grid = nt < per_cu * cus ? nt : per_cu * cus;
+    // two workgroups per CU keep enough accesses in flight for the few
+    // edges a phase has, and an eighth of the workgroups the barrier would
+    // have at full occupancy
+    const int cap_grid = (per_cu < 2 ? per_cu : 2) * cus;
+    const int grid = nt < cap_grid ? nt : cap_grid;
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, s, ctl, label_ctl_words(cap), 0u);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

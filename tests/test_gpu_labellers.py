@@ -9,6 +9,7 @@ dimensions, and at full size from ordered states where one cluster spans the
 lattice.  The iteration cap is a real bound: a cap of one scan cannot
 confirm convergence and the call reports SW_E_NOCONV."""
 import sys
+import time
 
 import numpy as np
 import pytest
@@ -72,7 +73,9 @@ def test_iterative_labeller_full_size_ordered(alg, name):
     lat.set_labeller(alg, 256)
     lat.set_state(st)
     lat.set_sweep_index(200)
+    t0 = time.perf_counter()
     lat.sweep(2)
+    say(f"[labeller {NAMES[alg]} full-ordered] {name}: 2 sweeps in {time.perf_counter() - t0:.3f} s")
     ref = oracle.sweeps(j["model"], j["dim"], j["L"], j["q"], j["beta"], j["seed"], j["replica"], 200, 2, st)
     assert np.bincount(ref["labels"]).max() > 0.1 * ref["labels"].size
     compare_lattice(j["model"], lat.get_state(), lat.get_labels(), lat.get_bonds(), ref)
