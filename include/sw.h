@@ -282,6 +282,12 @@ sw_handle sw_batch_member(sw_batch b, int j);
 /* Sweeps replayed per captured graph (default chosen by the tuner). */
 int sw_batch_set_chunk(sw_batch b, int sweeps_per_graph);
 
+/* Streams the batch's launches use (1 .. 8, default 2 when the batch has two
+ * lattices or more): the members are dealt to that many parts by site count,
+ * each part replaying its own graph on its own stream, so that the parts'
+ * kernels can run side by side.  The trajectories do not depend on it. */
+int sw_batch_set_streams(sw_batch b, int n);
+
 void sw_batch_destroy(sw_batch b);
 
 /* --- served form: continuous batching of submitted jobs ------------------- */

@@ -95,6 +95,7 @@ SIGNATURES = {
     "sw_batch_size": (i32, [vp]),
     "sw_batch_member": (vp, [vp, i32]),
     "sw_batch_set_chunk": (i32, [vp, i32]),
+    "sw_batch_set_streams": (i32, [vp, i32]),
     "sw_batch_destroy": (None, [vp]),
     "sw_server_create": (vp, [i64, i32, i32]),
     "sw_server_submit": (i64, [vp, vp]),
@@ -301,6 +302,9 @@ class Batch:
 
     def set_chunk(self, s):
         _check(lib().sw_batch_set_chunk(self.h, int(s)))
+
+    def set_streams(self, n):
+        _check(lib().sw_batch_set_streams(self.h, int(n)))
 
     def close(self):
         if self.h:

@@ -274,7 +274,9 @@ k_bond(const InstDesc *__restrict__ descs,
 
     const int2 tm = tmap[tile_slot()];
     if (tm.x < 0) return;
-    const InstDesc d = descs[tm.x];
+    // a reference: fields load from the (read-only) descriptor when used,
+    // instead of a copy that would hold them all in scalar registers
+    const InstDesc &d = descs[tm.x];
     if (k >= d.count) return;
     const uint32_t n = d.sweep0 + k;
     const int L = d.L;
@@ -1164,7 +1166,9 @@ __global__ void __launch_bounds__(64 * NW, (MODEL == XY) ? 4 : 8) k_flip(const I
     __shared__ uint32_t s_axis;
     const int2 tm = tmap[tile_slot()];
     if (tm.x < 0) return;
-    const InstDesc d = descs[tm.x];
+    // a reference: fields load from the (read-only) descriptor when used,
+    // instead of a copy that would hold them all in scalar registers
+    const InstDesc &d = descs[tm.x];
     if (k == FLIP_LAST) {
         if (d.count == 0) return;
         k = d.count - 1u;  // the chain's last sweep

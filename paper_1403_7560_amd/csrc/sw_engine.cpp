@@ -721,96 +721,147 @@ struct Group {
     int2 *d_tmap = nullptr;
 };
 
-struct sw_batch_s {
-    std::vector<std::unique_ptr<Lattice>> lats;
-    std::vector<std::unique_ptr<sw_ctx>> views;
+// The lattices of a batch are dealt to a few parts, each with its own
+// stream, descriptors, tile maps and captured graph: the parts' launches are
+// independent, so one part's latency-bound label merge can run beside
+// another part's bond kernel on the CUs the first leaves free.
+struct BatchPart {
+    std::vector<int> members;  // batch indices; the part's descriptor j is members[j]
     std::vector<Group> groups;
     InstDesc *d_desc = nullptr;
     InstDesc *h_desc = nullptr;  // pinned
-    uint32_t *d_err = nullptr;   // error word shared by the members' batched launches
     hipStream_t stream = nullptr;
-    int chunk = 16;
+    bool own_stream = false;
     hipGraphExec_t graph = nullptr;
     int graph_chunk = 0;
 
-    ~sw_batch_s()
+    ~BatchPart()
     {
         if (graph) (void)hipGraphExecDestroy(graph);
         for (Group &g : groups)
             if (g.d_tmap) (void)hipFree(g.d_tmap);
         if (d_desc) (void)hipFree(d_desc);
         if (h_desc) (void)hipHostFree(h_desc);
+        if (own_stream && stream) (void)hipStreamDestroy(stream);
+    }
+};
+
+struct sw_batch_s {
+    std::vector<std::unique_ptr<Lattice>> lats;
+    std::vector<std::unique_ptr<sw_ctx>> views;
+    std::vector<std::unique_ptr<BatchPart>> parts;
+    uint32_t *d_err = nullptr;   // error word shared by the members' batched launches
+    hipStream_t stream = nullptr;  // the batch's first stream (part 0's)
+    int chunk = 16;
+
+    ~sw_batch_s()
+    {
+        parts.clear();
         if (d_err) (void)hipFree(d_err);
         lats.clear();
         if (stream) (void)hipStreamDestroy(stream);
     }
 
-    int build_groups()
+    // Deal the lattices to n parts (largest first, each to the part with the
+    // fewest sites so far) and build every part's groups and tile maps.
+    int build_parts(int n)
     {
-        std::map<std::tuple<int, int, int>, int> index;
-        for (int j = 0; j < (int)lats.size(); ++j) {
-            const Lattice &l = *lats[j];
-            auto key = std::make_tuple(l.model, l.dim, l.variant);
-            auto it = index.find(key);
-            if (it == index.end()) {
-                index[key] = (int)groups.size();
-                groups.push_back(Group{l.model, l.dim, l.variant, {}, 0, 0, nullptr});
-                it = index.find(key);
+        if (stream) HIPCHK(hipStreamSynchronize(stream));
+        for (auto &pt : parts)
+            if (pt->stream) HIPCHK(hipStreamSynchronize(pt->stream));
+        parts.clear();
+        n = std::max(1, std::min<int>(n, (int)lats.size()));
+        std::vector<int> order((size_t)lats.size());
+        for (size_t j = 0; j < lats.size(); ++j) order[j] = (int)j;
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return lats[a]->N > lats[b]->N; });
+        std::vector<int64_t> load((size_t)n, 0);
+        for (int i = 0; i < n; ++i) parts.emplace_back(new BatchPart());
+        for (int j : order) {
+            const int p = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+            parts[p]->members.push_back(j);
+            load[p] += lats[j]->N;
+        }
+        for (int p = 0; p < n; ++p) {
+            BatchPart &pt = *parts[p];
+            std::sort(pt.members.begin(), pt.members.end());
+            if (p == 0) {
+                pt.stream = stream;
+            } else {
+                pt.stream = make_stream();
+                if (!pt.stream) return fail(SW_E_DEVICE, "hipStreamCreate failed");
+                pt.own_stream = true;
             }
-            groups[it->second].members.push_back(j);
+            std::map<std::tuple<int, int, int>, int> index;
+            for (int jl = 0; jl < (int)pt.members.size(); ++jl) {
+                Lattice &l = *lats[pt.members[jl]];
+                l.stream = pt.stream;  // the member's own calls run on its part's stream
+                views[pt.members[jl]]->stream = pt.stream;
+                auto key = std::make_tuple(l.model, l.dim, l.variant);
+                auto it = index.find(key);
+                if (it == index.end()) {
+                    index[key] = (int)pt.groups.size();
+                    pt.groups.push_back(Group{l.model, l.dim, l.variant, {}, 0, 0, nullptr});
+                    it = index.find(key);
+                }
+                pt.groups[it->second].members.push_back(jl);
+            }
+            for (Group &g : pt.groups) {
+                std::vector<int2> tm, cut;
+                for (int jl : g.members) append_tiles(*lats[pt.members[jl]], jl, tm, cut);
+                g.nfull = (int)tm.size();
+                tm.insert(tm.end(), cut.begin(), cut.end());
+                g.ntiles = (int)tm.size();
+                if (hipMalloc(&g.d_tmap, tm.size() * sizeof(int2)) != hipSuccess)
+                    return fail(SW_E_NOMEM, "tile map allocation failed");
+                HIPCHK(hipMemcpy(g.d_tmap, tm.data(), tm.size() * sizeof(int2), hipMemcpyHostToDevice));
+            }
+            const size_t m = pt.members.size();
+            if (hipMalloc(&pt.d_desc, m * sizeof(InstDesc)) != hipSuccess ||
+                hipHostMalloc(&pt.h_desc, m * sizeof(InstDesc), hipHostMallocDefault) != hipSuccess)
+                return fail(SW_E_NOMEM, "descriptor allocation failed");
         }
-        for (Group &g : groups) {
-            std::vector<int2> tm, cut;
-            for (int j : g.members) append_tiles(*lats[j], j, tm, cut);
-            g.nfull = (int)tm.size();
-            tm.insert(tm.end(), cut.begin(), cut.end());
-            g.ntiles = (int)tm.size();
-            if (hipMalloc(&g.d_tmap, tm.size() * sizeof(int2)) != hipSuccess)
-                return fail(SW_E_NOMEM, "tile map allocation failed");
-            HIPCHK(hipMemcpy(g.d_tmap, tm.data(), tm.size() * sizeof(int2), hipMemcpyHostToDevice));
+        if (!d_err) {
+            if (hipMalloc(&d_err, 256) != hipSuccess) return fail(SW_E_NOMEM, "error word allocation failed");
+            HIPCHK(hipMemset(d_err, 0, 256));
         }
-        if (hipMalloc(&d_desc, lats.size() * sizeof(InstDesc)) != hipSuccess ||
-            hipHostMalloc(&h_desc, lats.size() * sizeof(InstDesc), hipHostMallocDefault) != hipSuccess ||
-            hipMalloc(&d_err, 256) != hipSuccess)
-            return fail(SW_E_NOMEM, "descriptor allocation failed");
-        HIPCHK(hipMemset(d_err, 0, 256));
         return SW_OK;
     }
 
-    int enqueue_chunk(int S)
+    int enqueue_chunk(BatchPart &pt, int S)
     {
         for (int k = 0; k < S; ++k) {
-            for (const Group &g : groups)
-                HIPCHK(launch_bond(g.model, g.dim, g.variant, d_desc, g.d_tmap, g.ntiles, g.nfull, (uint32_t)k, 0, stream));
-            for (const Group &g : groups)
-                HIPCHK(launch_merge(g.dim, g.model, g.variant, d_desc, g.d_tmap, g.ntiles, (uint32_t)k, stream));
+            for (const Group &g : pt.groups)
+                HIPCHK(launch_bond(g.model, g.dim, g.variant, pt.d_desc, g.d_tmap, g.ntiles, g.nfull, (uint32_t)k, 0,
+                                   pt.stream));
+            for (const Group &g : pt.groups)
+                HIPCHK(launch_merge(g.dim, g.model, g.variant, pt.d_desc, g.d_tmap, g.ntiles, (uint32_t)k, pt.stream));
         }
-        for (const Group &g : groups)
-            HIPCHK(launch_flip(g.model, g.dim, g.variant, d_desc, g.d_tmap, g.ntiles, FLIP_LAST, stream));
-        HIPCHK(launch_advance(d_desc, (int)lats.size(), stream));
+        for (const Group &g : pt.groups)
+            HIPCHK(launch_flip(g.model, g.dim, g.variant, pt.d_desc, g.d_tmap, g.ntiles, FLIP_LAST, pt.stream));
+        HIPCHK(launch_advance(pt.d_desc, (int)pt.members.size(), pt.stream));
         return SW_OK;
     }
 
-    int capture(int S)
+    int capture(BatchPart &pt, int S)
     {
-        if (graph && graph_chunk == S) return SW_OK;
-        if (graph) {
-            (void)hipGraphExecDestroy(graph);
-            graph = nullptr;
+        if (pt.graph && pt.graph_chunk == S) return SW_OK;
+        if (pt.graph) {
+            (void)hipGraphExecDestroy(pt.graph);
+            pt.graph = nullptr;
         }
         hipGraph_t g = nullptr;
-        HIPCHK(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
-        int rc = enqueue_chunk(S);
-        hipError_t e = hipStreamEndCapture(stream, &g);
+        HIPCHK(hipStreamBeginCapture(pt.stream, hipStreamCaptureModeThreadLocal));
+        int rc = enqueue_chunk(pt, S);
+        hipError_t e = hipStreamEndCapture(pt.stream, &g);
         if (rc) {
             if (g) (void)hipGraphDestroy(g);
             return rc;
         }
         HIPCHK(e);
-        e = hipGraphInstantiate(&graph, g, nullptr, nullptr, 0);
+        e = hipGraphInstantiate(&pt.graph, g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
         HIPCHK(e);
-        graph_chunk = S;
+        pt.graph_chunk = S;
         return SW_OK;
     }
 
@@ -831,19 +882,30 @@ struct sw_batch_s {
                 int rc = l.grow_records(l.rec_count + counts[j]);
                 if (rc) return rc;
             }
-            InstDesc d = l.desc();
-            d.remaining = (uint32_t)counts[j];
-            d.chunk = (uint32_t)S;
-            d.count = (uint32_t)std::min<int64_t>(S, counts[j]);
-            d.err = d_err;
-            h_desc[j] = d;
         }
-        HIPCHK(hipMemcpyAsync(d_desc, h_desc, lats.size() * sizeof(InstDesc), hipMemcpyHostToDevice, stream));
-        int rc = capture(S);
-        if (rc) return rc;
-        const int64_t nchunks = (maxc + S - 1) / S;
-        for (int64_t c = 0; c < nchunks; ++c) HIPCHK(hipGraphLaunch(graph, stream));
-        HIPCHK(hipStreamSynchronize(stream));
+        // every part's chunks are queued before any wait: the parts run at once
+        for (auto &ptp : parts) {
+            BatchPart &pt = *ptp;
+            int64_t pmax = 0;
+            for (size_t jl = 0; jl < pt.members.size(); ++jl) {
+                const int j = pt.members[jl];
+                InstDesc d = lats[j]->desc();
+                d.remaining = (uint32_t)counts[j];
+                d.chunk = (uint32_t)S;
+                d.count = (uint32_t)std::min<int64_t>(S, counts[j]);
+                d.err = d_err;
+                pt.h_desc[jl] = d;
+                pmax = std::max(pmax, counts[j]);
+            }
+            if (pmax == 0) continue;
+            HIPCHK(hipMemcpyAsync(pt.d_desc, pt.h_desc, pt.members.size() * sizeof(InstDesc), hipMemcpyHostToDevice,
+                                  pt.stream));
+            int rc = capture(pt, S);
+            if (rc) return rc;
+            const int64_t nchunks = (pmax + S - 1) / S;
+            for (int64_t c = 0; c < nchunks; ++c) HIPCHK(hipGraphLaunch(pt.graph, pt.stream));
+        }
+        for (auto &ptp : parts) HIPCHK(hipStreamSynchronize(ptp->stream));
         for (size_t j = 0; j < lats.size(); ++j) {
             Lattice &l = *lats[j];
             if (counts[j] == 0) continue;
@@ -1394,7 +1456,7 @@ sw_batch sw_batch_create(const sw_job_desc *jobs, int n)
         b->views.push_back(std::move(v));
         b->lats.push_back(std::move(l));
     }
-    if (b->build_groups()) return nullptr;
+    if (b->build_parts(n >= 2 ? 2 : 1)) return nullptr;
     return b.release();
 }
 
@@ -1428,6 +1490,12 @@ int sw_batch_set_chunk(sw_batch b, int s)
     if (!b || s < 1 || s > 4096) return fail(SW_E_INVALID, "chunk must be in [1, 4096]");
     b->chunk = s;
     return SW_OK;
+}
+
+int sw_batch_set_streams(sw_batch b, int n)
+{
+    if (!b || n < 1 || n > 8) return fail(SW_E_INVALID, "streams must be in [1, 8]");
+    return b->build_parts(n);
 }
 
 void sw_batch_destroy(sw_batch b) { delete b; }
