@@ -202,6 +202,16 @@ int sw_get_label_stats(sw_handle h, int64_t *labellings, int64_t *scans, int64_t
  * SW_E_NOCONV, which is how the error path is exercised. */
 int sw_set_walk_cap(sw_handle h, int64_t cap);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * cluster statistics of sw_measure's last argument, computed without any
+ * allocation.  The per-root sizes live in a fixed device array of at most
+ * 2^22 sites (16 MiB, held by each GPU the library runs on until the process
+ * ends): lattices with more sites are rejected with SW_E_INVALID.  All calls
+ * on one GPU share that array, so calls that overlap on a GPU race; each
+ * call clears what it uses.  Synchronous on the handle's stream. */
+int sw_cluster_stats_noalloc(sw_handle h, sw_cluster_stats *cs);
+
 /* Drop the recorded series (the paper's discarded MCS). */
 int sw_reset_measure(sw_handle h);
 

@@ -75,6 +75,7 @@ SIGNATURES = {
     "sw_get_moments": (i32, [vp, vp]),
     "sw_set_walk_cap": (i32, [vp, i64]),
     "sw_set_labeller": (i32, [vp, i32, i32]),
+    "sw_cluster_stats_noalloc": (i32, [vp, vp]),
     "sw_get_label_stats": (i32, [vp, vp, vp, vp]),
     "sw_series": (i64, [vp, vp, i64]),
     "sw_set_measure": (i32, [vp, i32]),
@@ -219,6 +220,13 @@ class Lattice:
 
     def set_walk_cap(self, cap):
         _check(lib().sw_set_walk_cap(self.h, int(cap)))
+
+    def cluster_stats_noalloc(self):
+        """Cluster statistics of the last labelling through the allocation-free
+        entry point (sw_cluster_stats_noalloc)."""
+        cs = ClusterStats()
+        _check(lib().sw_cluster_stats_noalloc(self.h, ctypes.byref(cs)))
+        return {"n_clusters": cs.n_clusters, "max_cluster": cs.max_cluster, "sum_c2": cs.sum_c2}
 
     def reset_measure(self):
         _check(lib().sw_reset_measure(self.h))

@@ -1261,6 +1261,27 @@ int sw_get_moments(sw_handle h, sw_moments *out)
     return h->lat->moments(out);
 }
 
+int sw_cluster_stats_noalloc(sw_handle h, sw_cluster_stats *cs)
+{
+    CHECK_H(h);
+    if (!cs) return fail(SW_E_INVALID, "NULL output");
+    Lattice &l = *h->lat;
+    std::memset(cs, 0, sizeof(*cs));
+    if (l.N > STATIC_STATS_SITES)
+        return fail(SW_E_INVALID, "lattice has " + std::to_string(l.N) + " sites; the allocation-free cluster "
+                    "statistics hold at most " + std::to_string(STATIC_STATS_SITES));
+    if (l.labelled < 0) return SW_OK;
+    // its sweep index names the last labelled sweep's buffer
+    InstDesc d = l.labelled_desc();
+    HIPCHK(hipMemcpyAsync(l.d_solo, &d, sizeof(d), hipMemcpyHostToDevice, l.stream));
+    unsigned long long out[3] = {0, 0, 0};
+    HIPCHK(cluster_stats_static(l.d_solo, 0, l.N, out, l.stream));
+    cs->n_clusters = (int64_t)out[0];
+    cs->max_cluster = (int64_t)out[1];
+    cs->sum_c2 = (int64_t)out[2];
+    return l.check_errors();
+}
+
 int sw_set_labeller(sw_handle h, int algorithm, int max_iterations)
 {
     CHECK_H(h);

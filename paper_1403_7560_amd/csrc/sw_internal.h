@@ -130,4 +130,11 @@ namespace swmc {
 // out3 = {#clusters, max size, sum size^2}; must be zeroed by the caller.
 hipError_t launch_cluster_stats(const InstDesc *d_desc, int inst, int64_t N, int32_t *scratch,
                                 unsigned long long *out3, hipStream_t s);
+// The same without allocating: the scratch is a file-scope device array of
+// STATIC_STATS_SITES sites (hipErrorInvalidValue beyond); synchronous, the
+// three sums land in host_out.
+constexpr int64_t STATIC_STATS_SITES = (int64_t)1 << 22;
+constexpr int MAX_DEVICES = 64;
+hipError_t cluster_stats_static(const InstDesc *d_desc, int inst, int64_t N, unsigned long long host_out[3],
+                                hipStream_t s);
 }  // namespace swmc

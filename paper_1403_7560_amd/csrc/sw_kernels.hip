@@ -26,6 +26,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "sw_device.h"
 
 namespace swmc {
@@ -420,6 +422,60 @@ hipError_t launch_cluster_stats(const InstDesc *dd, int inst, int64_t N, int32_t
     hipLaunchKernelGGL(k_csize, dim3(grid), dim3(256), 0, s, dd, inst, scratch);
     hipLaunchKernelGGL(k_cstats, dim3(grid), dim3(256), 0, s, (const int32_t *)scratch, N, out3);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Cluster statistics without any allocation, for callers that cannot call
+// hipMalloc: the per-root sizes and the three sums live in one file-scope
+// device array of STATIC_STATS_SITES + 8 words (16 MiB), which each GPU holds
+// until the process ends.  Its name is a host-side stand-in in host code:
+// the device address comes from hipGetSymbolAddress, once per device with
+// that device current, and only that address is handed to kernels.  Every
+// call on a GPU shares the array (overlapping calls race); each call clears
+// what it uses.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) int32_t scratch[STATIC_STATS_SITES + 8];
+
+static std::mutex g_scratch_mu;
+static void *g_scratch_dev[MAX_DEVICES];
+
+static hipError_t scratch_address(int32_t **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_dev[dev] = p;
+    }
+    *out = (int32_t *)g_scratch_dev[dev];
+    return hipSuccess;
+}
+
+hipError_t cluster_stats_static(const InstDesc *dd, int inst, int64_t N, unsigned long long host_out[3],
+                                hipStream_t s)
+{
+    if (N < 1 || N > STATIC_STATS_SITES) return hipErrorInvalidValue;
+    int32_t *base = nullptr;
+    hipError_t e = scratch_address(&base);
+    if (e != hipSuccess) return e;
+    // sizes in words [0, N); the sums (three u64) after the last site slot,
+    // 8-byte aligned because STATIC_STATS_SITES is even
+    unsigned long long *out3 = (unsigned long long *)(base + STATIC_STATS_SITES);
+    const unsigned grid = (unsigned)((N + 255) / 256);
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid), dim3(256), 0, s, base, N, 0);
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(256), 0, s, base + STATIC_STATS_SITES, (int64_t)6, 0);
+    hipLaunchKernelGGL(k_csize, dim3(grid), dim3(256), 0, s, dd, inst, base);
+    hipLaunchKernelGGL(k_cstats, dim3(grid), dim3(256), 0, s, (const int32_t *)base, N, out3);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(host_out, out3, 3 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(s);
 }
 
 }  // namespace swmc
