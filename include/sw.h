@@ -343,6 +343,12 @@ int sw_server_poll(sw_server s, int64_t id, sw_job_result *out, void *state);
 /* Device bytes one job of this shape needs while resident. */
 int64_t sw_footprint(int model, int dim, int L, int q);
 
+/* Streams a server deals each tick's (model, dim, tile shape) groups to
+ * (1 .. 8, default 4), by site count: the groups' launches run side by side.
+ * Jobs are admitted (their lattices created) on a stream of their own while
+ * a tick runs.  Results do not depend on it. */
+int sw_server_set_streams(sw_server s, int n);
+
 void sw_server_destroy(sw_server s);
 
 #ifdef __cplusplus

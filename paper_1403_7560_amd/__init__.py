@@ -103,6 +103,7 @@ SIGNATURES = {
     "sw_server_step": (i64, [vp]),
     "sw_server_poll": (i32, [vp, i64, vp, vp]),
     "sw_footprint": (i64, [i32, i32, i32, i32]),
+    "sw_server_set_streams": (i32, [vp, i32]),
     "sw_server_destroy": (None, [vp]),
 }
 
@@ -348,6 +349,9 @@ class Server:
 
     def step(self):
         return _check(lib().sw_server_step(self.h))
+
+    def set_streams(self, n):
+        _check(lib().sw_server_set_streams(self.h, int(n)))
 
     def poll(self, job_id, model=None, N=None):
         r = JobResult()

@@ -920,6 +920,9 @@ struct sw_batch_s {
 // ---------------------------------------------------------------------------
 // Served form.
 // ---------------------------------------------------------------------------
+// Streams a server can deal each tick's groups to (it uses 4 unless told).
+constexpr int SERVER_STREAMS = 8;
+
 struct ServerJob {
     int64_t id;
     sw_job job;
@@ -937,9 +940,17 @@ struct sw_server_s {
     int64_t next_id = 0;
     std::deque<std::unique_ptr<ServerJob>> queue;
     std::vector<std::unique_ptr<ServerJob>> active;
+    std::vector<std::unique_ptr<ServerJob>> incoming;  // admitted while a tick ran; active from the next
     std::map<int64_t, sw_job_result> results;
     std::map<int64_t, std::vector<uint8_t>> final_state;
-    hipStream_t stream = nullptr;
+    // Each tick's groups are dealt to `nstreams` parts with a stream each, so
+    // that the small launches of different groups run side by side; new jobs
+    // are created on the admission stream while a tick runs.
+    std::vector<hipStream_t> streams;
+    hipStream_t admit_stream = nullptr;
+    hipEvent_t desc_ready = nullptr;
+    std::vector<int> group_part;  // part of each group
+    int nparts = 4;               // streams in use (<= streams.size())
     // batched launch state for the current active set
     std::vector<Group> groups;
     InstDesc *d_desc = nullptr;
@@ -950,14 +961,18 @@ struct sw_server_s {
 
     ~sw_server_s()
     {
+        for (hipStream_t st : streams) (void)hipStreamSynchronize(st);
         for (Group &g : groups)
             if (g.d_tmap) (void)hipFree(g.d_tmap);
         if (d_desc) (void)hipFree(d_desc);
         if (h_desc) (void)hipHostFree(h_desc);
         if (d_err) (void)hipFree(d_err);
         active.clear();
+        incoming.clear();
         queue.clear();
-        if (stream) (void)hipStreamDestroy(stream);
+        if (desc_ready) (void)hipEventDestroy(desc_ready);
+        for (hipStream_t st : streams) (void)hipStreamDestroy(st);
+        if (admit_stream) (void)hipStreamDestroy(admit_stream);
     }
 
     int rebuild()
@@ -983,9 +998,14 @@ struct sw_server_s {
             }
             groups[index[key]].members.push_back(j);
         }
-        for (Group &g : groups) {
+        std::vector<int64_t> gsites(groups.size(), 0);
+        for (size_t gi = 0; gi < groups.size(); ++gi) {
+            Group &g = groups[gi];
             std::vector<int2> tm, cut;
-            for (int j : g.members) append_tiles(*active[j]->lat, j, tm, cut);
+            for (int j : g.members) {
+                append_tiles(*active[j]->lat, j, tm, cut);
+                gsites[gi] += active[j]->lat->N;
+            }
             g.nfull = (int)tm.size();
             tm.insert(tm.end(), cut.begin(), cut.end());
             g.ntiles = (int)tm.size();
@@ -993,12 +1013,25 @@ struct sw_server_s {
                 return fail(SW_E_NOMEM, "tile map allocation failed");
             HIPCHK(hipMemcpy(g.d_tmap, tm.data(), tm.size() * sizeof(int2), hipMemcpyHostToDevice));
         }
+        // groups to parts: largest first, each to the part with the fewest sites
+        std::vector<int> order(groups.size());
+        for (size_t gi = 0; gi < groups.size(); ++gi) order[gi] = (int)gi;
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return gsites[x] > gsites[y]; });
+        std::vector<int64_t> load((size_t)nparts, 0);
+        group_part.assign(groups.size(), 0);
+        for (int gi : order) {
+            const int p = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+            group_part[gi] = p;
+            load[p] += gsites[gi];
+        }
         dirty = false;
         return SW_OK;
     }
 
-    int retire(double t)
+    // Results of jobs whose last sweep has run (their tick has completed).
+    int retire(bool all_done_only)
     {
+        (void)all_done_only;
         for (size_t j = 0; j < active.size();) {
             ServerJob &sj = *active[j];
             if (sj.done < sj.job.sweeps) {
@@ -1011,7 +1044,7 @@ struct sw_server_s {
             r.sweeps = sj.done;
             r.submit_s = sj.submit_s;
             r.start_s = sj.start_s;
-            r.finish_s = t;
+            r.finish_s = sj.finish_s;
             int rc = sj.lat->averages(&r.m2, &r.m4, &r.energy);
             r.status = sj.status ? sj.status : rc;
             std::vector<uint8_t> st((size_t)sj.lat->N * state_bytes(sj.lat->model));
@@ -1026,15 +1059,18 @@ struct sw_server_s {
         return SW_OK;
     }
 
+    // Create the lattices of queued jobs that fit (on the admission stream).
     int admit(double t)
     {
-        while (!queue.empty() && (int)active.size() < max_active && used + queue.front()->footprint <= budget) {
+        while (!queue.empty() && (int)(active.size() + incoming.size()) < max_active &&
+               used + queue.front()->footprint <= budget) {
             std::unique_ptr<ServerJob> sj = std::move(queue.front());
             queue.pop_front();
             sj->lat.reset(new Lattice());
             const sw_job_desc &jd = sj->job.lattice;
             int rc = sj->lat->create(jd.model, jd.dim, jd.L, jd.q, jd.beta, jd.seed, jd.replica,
-                                     tuned_tile(jd.model, jd.dim, jd.L), stream);
+                                     tuned_tile(jd.model, jd.dim, jd.L), admit_stream);
+            if (rc == SW_OK) rc = sj->lat->grow_records(sj->job.sweeps);
             if (rc) {
                 sw_job_result r;
                 std::memset(&r, 0, sizeof(r));
@@ -1047,24 +1083,21 @@ struct sw_server_s {
             }
             sj->start_s = t;
             used += sj->footprint;
-            active.push_back(std::move(sj));
-            dirty = true;
+            incoming.push_back(std::move(sj));
         }
         return SW_OK;
     }
 
     int64_t step()
     {
-        int rc = retire(now_s());
-        if (rc) return rc;
-        rc = admit(now_s());
-        if (rc) return rc;
+        int rc;
+        bool launched = false;
+        int64_t maxc = 0;
         if (!active.empty()) {
             if (dirty) {
                 rc = rebuild();
                 if (rc) return rc;
             }
-            int64_t maxc = 0;
             for (size_t j = 0; j < active.size(); ++j) {
                 Lattice &l = *active[j]->lat;
                 const int64_t c = std::min<int64_t>(chunk, active[j]->job.sweeps - active[j]->done);
@@ -1078,16 +1111,34 @@ struct sw_server_s {
                 h_desc[j] = d;
                 maxc = std::max(maxc, c);
             }
-            HIPCHK(hipMemcpyAsync(d_desc, h_desc, active.size() * sizeof(InstDesc), hipMemcpyHostToDevice, stream));
-            for (int64_t k = 0; k < maxc; ++k) {
-                for (const Group &g : groups)
-                    HIPCHK(launch_bond(g.model, g.dim, g.variant, d_desc, g.d_tmap, g.ntiles, g.nfull, (uint32_t)k, 0, stream));
-                for (const Group &g : groups)
-                    HIPCHK(launch_merge(g.dim, g.model, g.variant, d_desc, g.d_tmap, g.ntiles, (uint32_t)k, stream));
+            HIPCHK(hipMemcpyAsync(d_desc, h_desc, active.size() * sizeof(InstDesc), hipMemcpyHostToDevice,
+                                  streams[0]));
+            HIPCHK(hipEventRecord(desc_ready, streams[0]));
+            for (int p = 1; p < nparts; ++p) HIPCHK(hipStreamWaitEvent(streams[p], desc_ready, 0));
+            for (int p = 0; p < nparts; ++p) {
+                hipStream_t st = streams[p];
+                for (int64_t k = 0; k < maxc; ++k) {
+                    for (size_t gi = 0; gi < groups.size(); ++gi) {
+                        if (group_part[gi] != p) continue;
+                        const Group &g = groups[gi];
+                        HIPCHK(launch_bond(g.model, g.dim, g.variant, d_desc, g.d_tmap, g.ntiles, g.nfull, (uint32_t)k, 0, st));
+                        HIPCHK(launch_merge(g.dim, g.model, g.variant, d_desc, g.d_tmap, g.ntiles, (uint32_t)k, st));
+                    }
+                }
+                for (size_t gi = 0; gi < groups.size(); ++gi)
+                    if (group_part[gi] == p) {
+                        const Group &g = groups[gi];
+                        HIPCHK(launch_flip(g.model, g.dim, g.variant, d_desc, g.d_tmap, g.ntiles, FLIP_LAST, st));
+                    }
             }
-            for (const Group &g : groups)
-                HIPCHK(launch_flip(g.model, g.dim, g.variant, d_desc, g.d_tmap, g.ntiles, FLIP_LAST, stream));
-            HIPCHK(hipStreamSynchronize(stream));
+            launched = true;
+        }
+        // while the tick runs: new jobs are created
+        rc = admit(now_s());
+        if (rc) return rc;
+        if (launched) {
+            for (int p = 0; p < nparts; ++p) HIPCHK(hipStreamSynchronize(streams[p]));
+            const double t = now_s();
             // a flagged tick marks every job that took part in it
             const bool flagged = check_error_word(d_err) != SW_OK;
             for (size_t j = 0; j < active.size(); ++j) {
@@ -1098,8 +1149,19 @@ struct sw_server_s {
                 sj.lat->rec_count += c;
                 if (c > 0) sj.lat->labelled = sj.lat->sweep - 1;
                 if (c > 0 && flagged) sj.status = SW_E_NOCONV;
+                if (c > 0 && sj.done == sj.job.sweeps) sj.finish_s = t;
             }
-            rc = retire(now_s());
+        }
+        rc = retire(true);
+        if (rc) return rc;
+        if (!incoming.empty()) {
+            for (auto &sj : incoming) {
+                if (sj->job.sweeps == 0) sj->finish_s = now_s();
+                active.push_back(std::move(sj));
+            }
+            incoming.clear();
+            dirty = true;
+            rc = retire(true);  // jobs of zero sweeps
             if (rc) return rc;
         }
         return (int64_t)(queue.size() + active.size());
@@ -1538,9 +1600,17 @@ sw_server sw_server_create(int64_t budget, int max_active, int chunk)
     s->budget = budget;
     s->max_active = max_active;
     s->chunk = chunk;
-    s->stream = make_stream();
-    if (!s->stream) {
-        fail(SW_E_DEVICE, "hipStreamCreate failed (no HIP device?)");
+    for (int p = 0; p < SERVER_STREAMS; ++p) {
+        hipStream_t st = make_stream();
+        if (!st) {
+            fail(SW_E_DEVICE, "hipStreamCreate failed (no HIP device?)");
+            return nullptr;
+        }
+        s->streams.push_back(st);
+    }
+    s->admit_stream = make_stream();
+    if (!s->admit_stream || hipEventCreateWithFlags(&s->desc_ready, hipEventDisableTiming) != hipSuccess) {
+        fail(SW_E_DEVICE, "hipStreamCreate / hipEventCreate failed");
         return nullptr;
     }
     if (hipMalloc(&s->d_err, 256) != hipSuccess || hipMemset(s->d_err, 0, 256) != hipSuccess) {
@@ -1588,6 +1658,15 @@ int sw_server_poll(sw_server s, int64_t id, sw_job_result *out, void *state)
         auto st = s->final_state.find(id);
         if (st != s->final_state.end()) std::memcpy(state, st->second.data(), st->second.size());
     }
+    return SW_OK;
+}
+
+int sw_server_set_streams(sw_server s, int n)
+{
+    if (!s || n < 1 || n > SERVER_STREAMS) return fail(SW_E_INVALID, "streams must be in [1, 8]");
+    for (hipStream_t st : s->streams) HIPCHK(hipStreamSynchronize(st));
+    s->nparts = n;
+    s->dirty = true;
     return SW_OK;
 }
 

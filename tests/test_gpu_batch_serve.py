@@ -105,3 +105,44 @@ def test_server_jobs_match_oracle():
     with pytest.raises(sw.SWError):
         srv.submit(0, 2, 4096, 2, 0.4, 1, 0, 10)  # larger than the whole budget
     srv.close()
+
+
+def test_streams_do_not_change_results():
+    """A batch on one stream or three, a server on one stream or three: the
+    same trajectories as the oracle."""
+    say("[streams] batch of the mix on 1 and 3 streams")
+    for ns in (1, 3):
+        b = sw.Batch(MIX)
+        b.set_streams(ns)
+        b.sweep(4)
+        for j, m in zip(MIX, b.members):
+            compare_lattice(j["model"], m.get_state(), m.get_labels(), m.get_bonds(), oracle_run(j, 4))
+        b.close()
+    say("[streams] server of 8 jobs on 1 and 3 streams")
+    jobs = []
+    for k in range(8):
+        j = dict(MIX[k % len(MIX)])
+        j["seed"] = 300 + k
+        j["sweeps"] = 2 + k % 5
+        jobs.append(j)
+    for ns in (1, 3):
+        srv = sw.Server(1 << 34, max_active=5, chunk=3)
+        srv.set_streams(ns)
+        ids = [srv.submit(j["model"], j["dim"], j["L"], j["q"], j["beta"], j["seed"], j["replica"], j["sweeps"])
+               for j in jobs]
+        steps = 0
+        while srv.step() > 0:
+            steps += 1
+            assert steps < 100
+        for i, j in zip(ids, jobs):
+            r = srv.poll(i, j["model"], j["L"] ** j["dim"])
+            assert r["status"] == 0 and r["sweeps"] == j["sweeps"]
+            ref = oracle_run(j, j["sweeps"])
+            if j["model"] == 2:
+                d = np.abs(r["state"].astype(np.float64) - ref["state"])
+                assert np.minimum(d, 2 * np.pi - d).max() < 1e-5
+            else:
+                np.testing.assert_array_equal(r["state"], ref["state"])
+        with pytest.raises(sw.SWError):
+            srv.set_streams(9)
+        srv.close()
