@@ -206,13 +206,18 @@ def served(n_jobs, rate, seed=2014, plain=True):
     return out
 
 
-def timed_plain(sw, lattices, W, K, labeller=None):
+def timed_plain(sw, lattices, W, K, labeller=None, measure=True):
     """W warm-up and K timed sweeps of each lattice in the plain form, with
     HIP events (profile level 2) around the bond kernel and the global
     labelling phase of every 16th sweep and around each call's flip.
+    measure=False switches the per-sweep observables off (the paper's
+    "update" rows against "update + measurement").
     Returns (updates/ns, seconds, per-kernel block, lattices)."""
     lats = [sw.Lattice(j["model"], j["dim"], j["L"], j["q"], j["beta"], j["seed"], j["replica"])
             for j in lattices]
+    if not measure:
+        for lat in lats:
+            lat.set_measure(False)
     if labeller is not None:
         for lat in lats:
             lat.set_labeller(labeller, 256)
@@ -263,6 +268,16 @@ def leg_plain(sw, inputs, name, W, K, labeller=None):
         lat.close()
     return {"value": round(v, 3), "unit": "spin updates/ns", "ms_per_sweep": round(dt * 1e3 / K, 4),
             "steps": K, "warmup": W, "kernels": kernels}
+
+
+def update_only(sw, lattices, W, K):
+    """The plain-form leg of these lattices with the per-sweep measurement
+    switched off."""
+    v, dt, kernels, lats = timed_plain(sw, lattices, W, K, measure=False)
+    for lat in lats:
+        lat.close()
+    return {"value": round(v, 3), "ms_per_sweep": round(dt * 1e3 / K, 4),
+            "k_bond_us": (kernels or {}).get("k_bond", {}).get("avg_us")}
 
 
 def leg_batched(sw, inputs, name, W, K):
@@ -405,11 +420,17 @@ def main():
         out["paper_context"] = PAPER_CONTEXT[args.config]
     if args.config == "C2" and not args.quick:
         # the other workloads, compact (same step counts as the main line)
+        # the paper's tables give "update" and "update + measurement" rows:
+        # every plain leg measures each sweep; update_only is the same leg
+        # with the measurement off
+        out["update_only"] = dict(update_only(sw, lattices, W, K), workload="C2 pair, measurement off")
         out["c3_plain"] = dict(leg_plain(sw, inputs, "C3", W, K), workload=DESCRIPTION["C3"],
-                               paper_context=PAPER_CONTEXT["C3"])
+                               paper_context=PAPER_CONTEXT["C3"],
+                               update_only=update_only(sw, inputs.workload("C3")[0], W, K))
         out["c4_batched"] = dict(leg_batched(sw, inputs, "C4", W, K), workload=DESCRIPTION["C4"])
         out["clock_q512"] = dict(leg_plain(sw, inputs, "CLOCK-512", W, K), workload=DESCRIPTION["CLOCK"],
-                                 paper_context=PAPER_CONTEXT["CLOCK"])
+                                 paper_context=PAPER_CONTEXT["CLOCK"],
+                                 update_only=update_only(sw, inputs.workload("CLOCK-512")[0], W, K))
         c5 = {}
         # 300 jobs at the configured 200/s (the offered load is several times
         # what one GPU serves, so the latencies measure a growing queue), and

@@ -85,7 +85,8 @@ enum sw_status {
     SW_E_DEVICE = -3,  /* HIP runtime error (message in sw_last_error) */
     SW_E_NOCONV = -4,  /* labelling did not reach its fixed point within the cap */
     SW_E_BUSY = -5,    /* serving queue full / slot budget exhausted */
-    SW_E_NOTFOUND = -6 /* unknown job id */
+    SW_E_NOTFOUND = -6, /* unknown job id */
+    SW_E_CANCELLED = -7 /* status of a served job cancelled before its end */
 };
 
 typedef struct sw_ctx *sw_handle;
@@ -339,6 +340,15 @@ int64_t sw_server_step(sw_server s);
  * finished yet, 0 when copied).  With state != NULL the final configuration
  * is copied too (N states). */
 int sw_server_poll(sw_server s, int64_t id, sw_job_result *out, void *state);
+
+/* Cancel job `id` between ticks.  A queued job leaves the queue; a running
+ * one leaves the device at once and its memory returns to the budget.  Its
+ * result (sw_server_poll) then has status SW_E_CANCELLED, the sweeps it ran,
+ * the averages over them (0 when none ran) and the state after them (a job
+ * cancelled in the queue has no state: poll leaves the buffer untouched).
+ * Returns 0 when cancelled, 1 if the job had already finished (its result
+ * stays), SW_E_NOTFOUND for an unknown id. */
+int sw_server_cancel(sw_server s, int64_t id);
 
 /* Device bytes one job of this shape needs while resident. */
 int64_t sw_footprint(int model, int dim, int L, int q);

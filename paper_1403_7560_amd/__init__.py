@@ -16,7 +16,7 @@ ISING, POTTS, XY, CLOCK = 0, 1, 2, 3
 LABEL_HAWICK, LABEL_KALENTEV, LABEL_UNION = 0, 1, 2
 STATE_DTYPE = {ISING: np.int8, POTTS: np.uint8, XY: np.float32, CLOCK: np.uint16}
 ERRORS = {-1: "SW_E_INVALID", -2: "SW_E_NOMEM", -3: "SW_E_DEVICE", -4: "SW_E_NOCONV",
-          -5: "SW_E_BUSY", -6: "SW_E_NOTFOUND"}
+          -5: "SW_E_BUSY", -6: "SW_E_NOTFOUND", -7: "SW_E_CANCELLED"}
 
 
 class SWError(RuntimeError):
@@ -102,6 +102,7 @@ SIGNATURES = {
     "sw_server_submit": (i64, [vp, vp]),
     "sw_server_step": (i64, [vp]),
     "sw_server_poll": (i32, [vp, i64, vp, vp]),
+    "sw_server_cancel": (i32, [vp, i64]),
     "sw_footprint": (i64, [i32, i32, i32, i32]),
     "sw_server_set_streams": (i32, [vp, i32]),
     "sw_server_destroy": (None, [vp]),
@@ -352,6 +353,10 @@ class Server:
 
     def set_streams(self, n):
         _check(lib().sw_server_set_streams(self.h, int(n)))
+
+    def cancel(self, job_id):
+        """True when the job was cancelled, False if it had already finished."""
+        return _check(lib().sw_server_cancel(self.h, int(job_id))) == 0
 
     def poll(self, job_id, model=None, N=None):
         r = JobResult()

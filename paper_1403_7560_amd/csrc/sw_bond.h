@@ -3,6 +3,7 @@
 // shape).  Each model's instantiations are compiled in a translation unit of
 // their own (sw_bond_ising.hip, sw_bond_potts.hip, sw_bond_xy.hip).
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -1277,16 +1278,28 @@ __global__ void __launch_bounds__(64 * NW, (MODEL == XY) ? 4 : 8) k_flip(const I
 
 template <int MODEL, int DIM>
 static hipError_t bond_dispatch(int v, const InstDesc *dd, const int2 *tm, int nt, int nf, uint32_t k, int mode,
-                                hipStream_t s)
+                                hipStream_t s, hipEvent_t t0, hipEvent_t t1)
 {
+    // Full tiles first, then the tiles cut by the lattice edge. Timing events
+    // ride on the first and the last launch; untimed launches (and those a
+    // graph captures) take the plain launch path.
+    const bool timed = t0 != nullptr || t1 != nullptr;
+    const bool split = nf > 0 && nt > nf;
+#define LAUNCH(kern, grid, block, e0, e1, ...)                                                                 \
+    do {                                                                                                       \
+        if (timed)                                                                                             \
+            hipExtLaunchKernelGGL(kern, grid, block, 0, s, e0, e1, 0, __VA_ARGS__);                            \
+        else                                                                                                   \
+            hipLaunchKernelGGL(kern, grid, block, 0, s, __VA_ARGS__);                                          \
+    } while (0)
 #define X(i, a, b, c, w)                                                                                       \
     if (v == i) {                                                                                              \
         if (nf > 0)                                                                                            \
-            hipLaunchKernelGGL((k_bond<MODEL, DIM, a, b, c, w, true>), dim3(nf), dim3(64 * w), 0, s, dd, tm, k,  \
-                               mode);                                                                          \
+            LAUNCH((k_bond<MODEL, DIM, a, b, c, w, true>), dim3(nf), dim3(64 * w), t0, split ? nullptr : t1,     \
+                   dd, tm, k, mode);                                                                           \
         if (nt > nf)                                                                                           \
-            hipLaunchKernelGGL((k_bond<MODEL, DIM, a, b, c, w, false>), dim3(nt - nf), dim3(64 * w), 0, s, dd,   \
-                               tm + nf, k, mode);                                                              \
+            LAUNCH((k_bond<MODEL, DIM, a, b, c, w, false>), dim3(nt - nf), dim3(64 * w), split ? nullptr : t0,   \
+                   t1, dd, tm + nf, k, mode);                                                                  \
         return hipGetLastError();                                                                              \
     }
     if constexpr (MODEL < XY && DIM == 2) { SW_VARIANTS_ISING2 }
@@ -1294,6 +1307,7 @@ static hipError_t bond_dispatch(int v, const InstDesc *dd, const int2 *tm, int n
     if constexpr (MODEL >= XY && DIM == 2) { SW_VARIANTS_XY2 }
     if constexpr (MODEL >= XY && DIM == 3) { SW_VARIANTS_XY3 }
 #undef X
+#undef LAUNCH
     return hipErrorInvalidValue;
 }
 

@@ -4,10 +4,10 @@
 namespace swmc {
 
 hipError_t launch_bond_potts(int dim, int v, const InstDesc *dd, const int2 *tm, int nt, int nf, uint32_t k,
-                          int mode, hipStream_t s)
+                             int mode, hipStream_t s, hipEvent_t t0, hipEvent_t t1)
 {
-    return dim == 2 ? bond_dispatch<POTTS, 2>(v, dd, tm, nt, nf, k, mode, s)
-                    : bond_dispatch<POTTS, 3>(v, dd, tm, nt, nf, k, mode, s);
+    return dim == 2 ? bond_dispatch<POTTS, 2>(v, dd, tm, nt, nf, k, mode, s, t0, t1)
+                    : bond_dispatch<POTTS, 3>(v, dd, tm, nt, nf, k, mode, s, t0, t1);
 }
 
 hipError_t launch_flip_potts(int dim, int v, const InstDesc *dd, const int2 *tm, int nt, uint32_t k,

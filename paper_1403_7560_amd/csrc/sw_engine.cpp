@@ -469,9 +469,9 @@ struct Lattice {
             for (int64_t k = 0; k < m; ++k) {
                 const bool timed = profiling && k >= first_timed && (k - first_timed) % PROFILE_EVERY == 0;
                 hipEvent_t *ev = timed ? &events[(size_t)(4 * ((k - first_timed) / PROFILE_EVERY))] : nullptr;
-                if (ev) HIPCHK(hipEventRecord(ev[0], stream));
-                HIPCHK(launch_bond(model, dim, variant, d_solo, d_tmap, ntiles, nfull, (uint32_t)k, 0, stream));
-                if (ev) HIPCHK(hipEventRecord(ev[1], stream));
+                // the bond launch records ev[0] / ev[1] itself (its own start and end)
+                HIPCHK(launch_bond(model, dim, variant, d_solo, d_tmap, ntiles, nfull, (uint32_t)k, 0, stream,
+                                   ev ? ev[0] : nullptr, ev ? ev[1] : nullptr));
                 HIPCHK(launch_global((uint32_t)k));
                 if (ev && profiling > 1) HIPCHK(hipEventRecord(ev[2], stream));
             }
@@ -1057,6 +1057,49 @@ struct sw_server_s {
             dirty = true;
         }
         return SW_OK;
+    }
+
+    // Cancel job `id`. Between ticks no work of any job is in flight (a tick
+    // ends with its streams synchronised and admission synchronises the new
+    // lattice), so a queued job simply leaves the queue and a running one
+    // leaves the active set at once, its budget freed. The result of a
+    // running job keeps the sweeps it ran, their averages and its state.
+    int cancel(int64_t id)
+    {
+        if (results.count(id)) return 1;
+        sw_job_result r;
+        std::memset(&r, 0, sizeof(r));
+        r.id = id;
+        r.status = SW_E_CANCELLED;
+        for (auto it = queue.begin(); it != queue.end(); ++it) {
+            if ((*it)->id != id) continue;
+            r.submit_s = (*it)->submit_s;
+            r.start_s = r.finish_s = now_s();
+            results[id] = r;
+            queue.erase(it);
+            return SW_OK;
+        }
+        for (size_t j = 0; j < active.size(); ++j) {
+            ServerJob &sj = *active[j];
+            if (sj.id != id) continue;
+            r.sweeps = sj.done;
+            r.submit_s = sj.submit_s;
+            r.start_s = sj.start_s;
+            r.finish_s = now_s();
+            if (sj.done > 0) {
+                int rc = sj.lat->averages(&r.m2, &r.m4, &r.energy);
+                if (rc) return rc;
+            }
+            std::vector<uint8_t> st((size_t)sj.lat->N * state_bytes(sj.lat->model));
+            HIPCHK(hipMemcpy(st.data(), sj.lat->state, st.size(), hipMemcpyDeviceToHost));
+            final_state[id] = std::move(st);
+            results[id] = r;
+            used -= sj.footprint;
+            active.erase(active.begin() + j);
+            dirty = true;
+            return SW_OK;
+        }
+        return fail(SW_E_NOTFOUND, "unknown job id");
     }
 
     // Create the lattices of queued jobs that fit (on the admission stream).
@@ -1659,6 +1702,12 @@ int sw_server_poll(sw_server s, int64_t id, sw_job_result *out, void *state)
         if (st != s->final_state.end()) std::memcpy(state, st->second.data(), st->second.size());
     }
     return SW_OK;
+}
+
+int sw_server_cancel(sw_server s, int64_t id)
+{
+    if (!s) return fail(SW_E_INVALID, "NULL server");
+    return s->cancel(id);
 }
 
 int sw_server_set_streams(sw_server s, int n)

@@ -91,8 +91,12 @@ bool tile_interior(int dim, int L, const TileShape &ts, int t);
 hipError_t launch_init(const InstDesc *d_desc, int inst, const InstDesc &h, hipStream_t s);
 // The first `nfull` entries of the tile map are tiles wholly inside their
 // lattice (see append_tiles); they run the bond kernel without edge tests.
+// `t0`/`t1` (may be null) are recorded by the launches themselves: t0 when
+// the first bond launch starts executing, t1 when the last one ends, so their
+// elapsed time is the kernel's own duration without the gaps around it.
 hipError_t launch_bond(int model, int dim, int variant, const InstDesc *d_desc,
-                       const int2 *d_tmap, int ntiles, int nfull, uint32_t k, int mode, hipStream_t s);
+                       const int2 *d_tmap, int ntiles, int nfull, uint32_t k, int mode, hipStream_t s,
+                       hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 hipError_t launch_merge(int dim, int model, int variant, const InstDesc *d_desc, const int2 *d_tmap,
                         int ntiles, uint32_t k, hipStream_t s);
 hipError_t launch_reduce(int model, const InstDesc *d_desc, const int2 *d_tmap, int ntiles, hipStream_t s);
@@ -104,16 +108,16 @@ hipError_t launch_advance(InstDesc *d_desc, int ninst, hipStream_t s);
 // Per-model instantiations behind launch_bond / launch_flip (one translation
 // unit each).
 hipError_t launch_bond_ising(int dim, int v, const InstDesc *dd, const int2 *tm, int nt, int nf, uint32_t k,
-                             int mode, hipStream_t s);
+                             int mode, hipStream_t s, hipEvent_t t0, hipEvent_t t1);
 hipError_t launch_bond_potts(int dim, int v, const InstDesc *dd, const int2 *tm, int nt, int nf, uint32_t k,
-                             int mode, hipStream_t s);
+                             int mode, hipStream_t s, hipEvent_t t0, hipEvent_t t1);
 hipError_t launch_bond_xy(int dim, int v, const InstDesc *dd, const int2 *tm, int nt, int nf, uint32_t k,
-                          int mode, hipStream_t s);
+                          int mode, hipStream_t s, hipEvent_t t0, hipEvent_t t1);
 hipError_t launch_flip_ising(int dim, int v, const InstDesc *dd, const int2 *tm, int nt, uint32_t k, hipStream_t s);
 hipError_t launch_flip_potts(int dim, int v, const InstDesc *dd, const int2 *tm, int nt, uint32_t k, hipStream_t s);
 hipError_t launch_flip_xy(int dim, int v, const InstDesc *dd, const int2 *tm, int nt, uint32_t k, hipStream_t s);
 hipError_t launch_bond_clock(int dim, int v, const InstDesc *dd, const int2 *tm, int nt, int nf, uint32_t k,
-                             int mode, hipStream_t s);
+                             int mode, hipStream_t s, hipEvent_t t0, hipEvent_t t1);
 hipError_t launch_flip_clock(int dim, int v, const InstDesc *dd, const int2 *tm, int nt, uint32_t k, hipStream_t s);
 
 // The paper's iterative labellers for the global phase (alg 0 Hawick, 1

@@ -309,14 +309,14 @@ hipError_t launch_reduce(int model, const InstDesc *dd, const int2 *tm, int nt, 
 }
 
 hipError_t launch_bond(int model, int dim, int v, const InstDesc *dd, const int2 *tm, int nt, int nf, uint32_t k,
-                       int mode, hipStream_t s)
+                       int mode, hipStream_t s, hipEvent_t t0, hipEvent_t t1)
 {
     if (nt <= 0) return hipSuccess;
     if (nf < 0 || nf > nt) return hipErrorInvalidValue;
-    if (model == ISING) return launch_bond_ising(dim, v, dd, tm, nt, nf, k, mode, s);
-    if (model == POTTS) return launch_bond_potts(dim, v, dd, tm, nt, nf, k, mode, s);
-    if (model == XY) return launch_bond_xy(dim, v, dd, tm, nt, nf, k, mode, s);
-    return launch_bond_clock(dim, v, dd, tm, nt, nf, k, mode, s);
+    if (model == ISING) return launch_bond_ising(dim, v, dd, tm, nt, nf, k, mode, s, t0, t1);
+    if (model == POTTS) return launch_bond_potts(dim, v, dd, tm, nt, nf, k, mode, s, t0, t1);
+    if (model == XY) return launch_bond_xy(dim, v, dd, tm, nt, nf, k, mode, s, t0, t1);
+    return launch_bond_clock(dim, v, dd, tm, nt, nf, k, mode, s, t0, t1);
 }
 
 hipError_t launch_flip(int model, int dim, int v, const InstDesc *dd, const int2 *tm, int nt, uint32_t k,

@@ -146,3 +146,51 @@ def test_streams_do_not_change_results():
         with pytest.raises(sw.SWError):
             srv.set_streams(9)
         srv.close()
+
+
+def test_server_cancel():
+    """A job cancelled while it runs keeps the sweeps it ran (state and
+    averages as the oracle's after them); one cancelled in the queue never
+    runs; the others finish as if alone."""
+    say("[serve] cancel a running and a queued job")
+    jobs = []
+    for k in range(4):
+        j = dict(MIX[k])
+        j["seed"] = 500 + k
+        j["sweeps"] = 10
+        jobs.append(j)
+    srv = sw.Server(1 << 34, max_active=2, chunk=3)
+    ids = [srv.submit(j["model"], j["dim"], j["L"], j["q"], j["beta"], j["seed"], j["replica"], j["sweeps"])
+           for j in jobs]
+    srv.step()  # admits jobs 0 and 1
+    srv.step()  # runs their first 3 sweeps
+    assert srv.cancel(ids[0]) is True
+    assert srv.cancel(ids[3]) is True
+    assert srv.cancel(ids[0]) is False
+    with pytest.raises(sw.SWError) as e:
+        srv.cancel(12345)
+    assert e.value.code == -6
+    j0 = jobs[0]
+    r = srv.poll(ids[0], j0["model"], j0["L"] ** j0["dim"])
+    assert r["status"] == -7 and r["sweeps"] == 3
+    ref = oracle_run(j0, 3)
+    np.testing.assert_array_equal(r["state"], ref["state"])
+    N = j0["L"] ** j0["dim"]
+    assert r["m2"] == pytest.approx(np.mean((ref["records"]["mx"] / N) ** 2), rel=1e-9)
+    r3 = srv.poll(ids[3])
+    assert r3["status"] == -7 and r3["sweeps"] == 0
+    steps = 0
+    while srv.step() > 0:
+        steps += 1
+        assert steps < 100
+    for i in (1, 2):
+        j = jobs[i]
+        r = srv.poll(ids[i], j["model"], j["L"] ** j["dim"])
+        assert r["status"] == 0 and r["sweeps"] == 10
+        ref = oracle_run(j, 10)
+        if j["model"] == 2:
+            d = np.abs(r["state"].astype(np.float64) - ref["state"])
+            assert np.minimum(d, 2 * np.pi - d).max() < 1e-5
+        else:
+            np.testing.assert_array_equal(r["state"], ref["state"])
+    srv.close()
