@@ -139,6 +139,106 @@ __device__ __forceinline__ bool gunion(uint32_t *lab, uint32_t a, uint32_t b, ui
     }
 }
 
+// Insert the pair (a, b) into an LDS hash set of mask + 1 slots (empty slots
+// hold all ones).  True when this call inserted it (or found no free slot
+// within eight probes): the caller links the pair; false when it was there.
+__device__ __forceinline__ bool insert_pair(unsigned long long *set, uint32_t mask, uint32_t a, uint32_t b)
+{
+    const unsigned long long key = ((unsigned long long)a << 32) | b;
+    uint32_t h = (a * 0x9E3779B1u) ^ (b * 0x85EBCA77u);
+    for (int probe = 0; probe < 8; ++probe) {
+        h = (h + (uint32_t)probe) & mask;
+        const unsigned long long old = atomicCAS(&set[h], ~0ull, key);
+        if (old == ~0ull) return true;
+        if (old == key) return false;
+    }
+    return true;
+}
+
+// The unions of up to E pairs of one thread, advanced together: each round
+// takes one path-halving find step (as gfind) on both sides of every pending
+// pair, the loads of all pairs in flight at once, then links every pair
+// whose two sides have reached their roots with atomicMin (larger root under
+// smaller), again all at once.  A link that finds its target linked
+// meanwhile continues from the word it read, as gunion does.  So a thread's
+// chains overlap instead of running one after the other.  Returns false
+// when the rounds exceed `budget` (a valid forest never gets there).
+template <int E>
+__device__ __forceinline__ bool gunion_batch(uint32_t *lab, uint32_t (&x)[E], uint32_t (&y)[E], bool (&act)[E],
+                                             uint32_t budget)
+{
+    bool any = false;
+#pragma unroll
+    for (int i = 0; i < E; ++i) any |= act[i];
+    while (any) {
+        if (budget == 0u) return false;
+        --budget;
+        uint32_t px[E], py[E], gx[E], gy[E];
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            px[i] = py[i] = ROOT_FLAG;
+            if (act[i]) {
+                px[i] = glabel_load(lab + x[i]);
+                py[i] = glabel_load(lab + y[i]);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            gx[i] = (px[i] & ROOT_FLAG) ? px[i] : glabel_load(lab + px[i]);
+            gy[i] = (py[i] & ROOT_FLAG) ? py[i] : glabel_load(lab + py[i]);
+        }
+        bool link[E];
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            link[i] = false;
+            if (!act[i]) continue;
+            if (!(px[i] & ROOT_FLAG)) {
+                if (gx[i] & ROOT_FLAG) {
+                    x[i] = px[i];
+                } else {
+                    glabel_store(lab + x[i], gx[i]);
+                    x[i] = gx[i];
+                }
+            }
+            if (!(py[i] & ROOT_FLAG)) {
+                if (gy[i] & ROOT_FLAG) {
+                    y[i] = py[i];
+                } else {
+                    glabel_store(lab + y[i], gy[i]);
+                    y[i] = gy[i];
+                }
+            }
+            const bool rx = (px[i] & ROOT_FLAG) || (gx[i] & ROOT_FLAG);
+            const bool ry = (py[i] & ROOT_FLAG) || (gy[i] & ROOT_FLAG);
+            if (rx && ry) {
+                if (x[i] == y[i]) act[i] = false;
+                else link[i] = true;
+            }
+        }
+        uint32_t old[E];
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            old[i] = ROOT_FLAG;
+            if (link[i]) {
+                const uint32_t hi = max(x[i], y[i]), lo = min(x[i], y[i]);
+                // roots hold ROOT_FLAG|decision > any index: atomicMin links a root
+                old[i] = atomicMin(lab + hi, lo);
+                y[i] = lo;
+            }
+        }
+        any = false;
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            if (link[i]) {
+                if (old[i] & ROOT_FLAG) act[i] = false;
+                else x[i] = old[i];  // linked meanwhile: join what it points at with lo
+            }
+            any |= act[i];
+        }
+    }
+    return true;
+}
+
 // Record a capped walk in the lattice's error word.
 __device__ __forceinline__ void flag_error(const InstDesc &d, uint32_t bit)
 {
@@ -210,19 +310,21 @@ __device__ __forceinline__ uint32_t from_left(uint32_t v)
 // ---------------------------------------------------------------------------
 // Reduction of the per-tile measurement partials into one record row, in a
 // fixed order (deterministic, also for the XY sums).  Workgroup t of a
-// lattice reduces slots t, t + ntiles, ... (XY: workgroup 0 all three).
+// lattice (NT threads) reduces slots t, t + ntiles, ... (XY: workgroup 0 all
+// three).
 // ---------------------------------------------------------------------------
-template <int MODEL>
+template <int MODEL, int NT>
 __device__ void reduce_partials(const InstDesc &d, int t, int64_t row)
 {
-    __shared__ double s_red[4][3];
+    constexpr int NW = NT / 64;
+    __shared__ double s_red[NW][3];
     const int tid = threadIdx.x, wv = tid >> 6, ln = tid & 63;
     GLOBAL int64_t *rec = (GLOBAL int64_t *)d.rec + row * d.nslots;
     const GLOBAL int64_t *part = (const GLOBAL int64_t *)d.part;
     if (MODEL == XY) {
         if (t != 0) return;
         double acc[3] = {0.0, 0.0, 0.0};
-        for (int tt = tid; tt < d.ntiles; tt += 256)
+        for (int tt = tid; tt < d.ntiles; tt += NT)
             for (int c = 0; c < 3; ++c) acc[c] += __longlong_as_double(part[(int64_t)tt * 3 + c]);
         for (int c = 0; c < 3; ++c) {
             const double v = wave_sum_d(acc[c]);
@@ -230,8 +332,9 @@ __device__ void reduce_partials(const InstDesc &d, int t, int64_t row)
         }
         __syncthreads();
         if (tid == 0) {
-            double v[3];
-            for (int c = 0; c < 3; ++c) v[c] = ((s_red[0][c] + s_red[1][c]) + s_red[2][c]) + s_red[3][c];
+            double v[3] = {0.0, 0.0, 0.0};
+            for (int w = 0; w < NW; ++w)
+                for (int c = 0; c < 3; ++c) v[c] += s_red[w][c];
             rec[0] = __double_as_longlong(v[0]);
             rec[1] = __double_as_longlong(v[1]);
             rec[2] = __double_as_longlong(v[2]);
@@ -241,14 +344,15 @@ __device__ void reduce_partials(const InstDesc &d, int t, int64_t row)
     }
     for (int slot = t; slot < d.nslots; slot += d.ntiles) {
         long long acc = 0;
-        for (int tt = tid; tt < d.ntiles; tt += 256) acc += part[(int64_t)tt * d.nslots + slot];
+        for (int tt = tid; tt < d.ntiles; tt += NT) acc += part[(int64_t)tt * d.nslots + slot];
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
         if (ln == 0) s_red[wv][0] = __longlong_as_double(acc);
         __syncthreads();
         if (tid == 0) {
-            rec[slot] = __double_as_longlong(s_red[0][0]) + __double_as_longlong(s_red[1][0]) +
-                        __double_as_longlong(s_red[2][0]) + __double_as_longlong(s_red[3][0]);
+            long long v = 0;
+            for (int w = 0; w < NW; ++w) v += __double_as_longlong(s_red[w][0]);
+            rec[slot] = v;
         }
         __syncthreads();
     }

@@ -72,14 +72,17 @@ __global__ void __launch_bounds__(256) k_init(const InstDesc *__restrict__ descs
 // unique in an LDS hash set (the face element before each one is compared
 // first, which removes most repeats without touching the set); the thread
 // that inserts a pair links it.  All face elements of the tile are loaded at
-// once, before any link.  The first workgroups of a lattice also reduce the
-// sweep's measurement partials.
+// once, before any link, and a thread's links advance together
+// (gunion_batch).  NT threads per workgroup: 128 when a 2D tile has at most
+// 128 face elements (so that a CU holds twice the tiles), else 256.  The
+// first workgroups of a lattice also reduce the sweep's measurement
+// partials.
 // ---------------------------------------------------------------------------
-template <int DIM, int EMAX>
-__global__ void __launch_bounds__(256) k_merge(const InstDesc *__restrict__ descs,
-                                               const int2 *__restrict__ tmap, uint32_t k)
+template <int DIM, int EMAX, int NT>
+__global__ void __launch_bounds__(NT) k_merge(const InstDesc *__restrict__ descs,
+                                              const int2 *__restrict__ tmap, uint32_t k)
 {
-    // EMAX: face elements per thread (the tile shape's faces over 256 threads)
+    // EMAX: face elements per thread (the tile shape's faces over NT threads)
     constexpr int HB = (DIM == 2) ? 512 : 2048;  // hash slots (about the face elements with a bond)
     constexpr unsigned long long EMPTY = ~0ull;
     __shared__ unsigned long long s_set[HB];
@@ -92,12 +95,12 @@ __global__ void __launch_bounds__(256) k_merge(const InstDesc *__restrict__ desc
     // the first workgroups of a lattice also reduce the sweep's measurement
     if (d.measure && d.rec_row0 >= 0 && d.rec_row0 + (int64_t)k < d.rec_cap &&
         (t < d.nslots || (d.model >= XY && t == 0))) {
-        if (d.model == ISING) reduce_partials<ISING>(d, t, d.rec_row0 + (int64_t)k);
-        else if (d.model == POTTS) reduce_partials<POTTS>(d, t, d.rec_row0 + (int64_t)k);
-        else reduce_partials<XY>(d, t, d.rec_row0 + (int64_t)k);
+        if (d.model == ISING) reduce_partials<ISING, NT>(d, t, d.rec_row0 + (int64_t)k);
+        else if (d.model == POTTS) reduce_partials<POTTS, NT>(d, t, d.rec_row0 + (int64_t)k);
+        else reduce_partials<XY, NT>(d, t, d.rec_row0 + (int64_t)k);
     }
     uint32_t *lab = labels_of(d, d.sweep0 + k);
-    for (int h = tid; h < HB; h += 256) s_set[h] = EMPTY;
+    for (int h = tid; h < HB; h += NT) s_set[h] = EMPTY;
     // the faces with a neighbour tile, one after the other in element order
     const int tc[3] = {t % d.tiles[0], (t / d.tiles[0]) % d.tiles[1],
                        (DIM == 3) ? t / (d.tiles[0] * d.tiles[1]) : 0};
@@ -121,7 +124,7 @@ __global__ void __launch_bounds__(256) k_merge(const InstDesc *__restrict__ desc
     bool first[EMAX];
 #pragma unroll
     for (int i = 0; i < EMAX; ++i) {
-        const int e = tid + 256 * i;
+        const int e = tid + NT * i;
         a[i] = b[i] = pa[i] = pb[i] = -1;
         first[i] = true;
         if (e < total) {
@@ -152,9 +155,15 @@ __global__ void __launch_bounds__(256) k_merge(const InstDesc *__restrict__ desc
         }
     }
     __syncthreads();  // hash set cleared
+    // the unique pairs this thread inserted are the ones it links
+    uint32_t x[EMAX], y[EMAX];
+    bool act[EMAX];
 #pragma unroll
     for (int i = 0; i < EMAX; ++i) {
-        if (256 * i >= total) break;  // uniform
+        act[i] = false;
+        x[i] = (uint32_t)a[i];
+        y[i] = (uint32_t)b[i];
+        if (NT * i >= total) continue;  // uniform
         const int32_t la = (int32_t)from_left((uint32_t)a[i]), lb = (int32_t)from_left((uint32_t)b[i]);
         if ((tid & 63) != 0) {
             pa[i] = la;
@@ -162,20 +171,9 @@ __global__ void __launch_bounds__(256) k_merge(const InstDesc *__restrict__ desc
         }
         if (a[i] < 0) continue;
         if (!first[i] && pa[i] == a[i] && pb[i] == b[i]) continue;  // same pair as the element before
-        const unsigned long long key = ((unsigned long long)(uint32_t)a[i] << 32) | (uint32_t)b[i];
-        uint32_t h = ((uint32_t)a[i] * 0x9E3779B1u) ^ ((uint32_t)b[i] * 0x85EBCA77u);
-        bool fresh = true;
-        for (int probe = 0; probe < 8; ++probe) {
-            h = (h + (uint32_t)probe) & (HB - 1);
-            const unsigned long long old = atomicCAS(&s_set[h], EMPTY, key);
-            if (old == EMPTY) break;  // inserted: this thread links the pair
-            if (old == key) {
-                fresh = false;  // seen before in this tile
-                break;
-            }
-        }
-        if (fresh && !gunion(lab, (uint32_t)a[i], (uint32_t)b[i], d.walk_cap)) flag_error(d, ERR_WALK);
+        act[i] = insert_pair(s_set, HB - 1, (uint32_t)a[i], (uint32_t)b[i]);
     }
+    if (!gunion_batch<EMAX>(lab, x, y, act, d.walk_cap)) flag_error(d, ERR_WALK);
 }
 
 // Measurement of the current configuration alone: reduce into the scratch row.
@@ -186,7 +184,7 @@ __global__ void __launch_bounds__(256) k_reduce(const InstDesc *__restrict__ des
     if (tm.x < 0) return;
     const InstDesc &d = descs[tm.x];
     if (tm.y >= d.nslots && !(MODEL == XY && tm.y == 0)) return;
-    reduce_partials<MODEL>(d, tm.y, d.rec_cap);
+    reduce_partials<MODEL, 256>(d, tm.y, d.rec_cap);
 }
 
 // Minimum-index labels: follow every chain to its root.
@@ -279,8 +277,9 @@ static hipError_t merge_dispatch(int v, const InstDesc *dd, const int2 *tm, int 
     // face elements of a tile: +x face TY TZ, +y face TX TZ, +z face TX TY
 #define X(i, a, b, c, w)                                                                                   \
     if (v == i) {                                                                                          \
-        constexpr int E = ((b) * (c) + (a) * (c) + (DIM == 3 ? (a) * (b) : 0) + 255) / 256;                \
-        hipLaunchKernelGGL((k_merge<DIM, E>), dim3(nt), dim3(256), 0, s, dd, tm, k);                      \
+        constexpr int FT = (b) * (c) + (a) * (c) + (DIM == 3 ? (a) * (b) : 0);                            \
+        constexpr int NTM = (DIM == 2 && FT <= 128) ? 128 : 256;                                           \
+        hipLaunchKernelGGL((k_merge<DIM, (FT + NTM - 1) / NTM, NTM>), dim3(nt), dim3(NTM), 0, s, dd, tm, k); \
         return hipGetLastError();                                                                          \
     }
     if constexpr (MODEL < XY && DIM == 2) { SW_VARIANTS_ISING2 }

@@ -125,9 +125,9 @@ __global__ void __launch_bounds__(256) k_label_iter(const InstDesc *__restrict__
         // the first workgroups of a lattice also reduce the sweep's measurement
         if (d.measure && d.rec_row0 >= 0 && d.rec_row0 + (int64_t)k < d.rec_cap &&
             (t < d.nslots || (d.model >= XY && t == 0))) {
-            if (d.model == ISING) reduce_partials<ISING>(d, t, d.rec_row0 + (int64_t)k);
-            else if (d.model == POTTS) reduce_partials<POTTS>(d, t, d.rec_row0 + (int64_t)k);
-            else reduce_partials<XY>(d, t, d.rec_row0 + (int64_t)k);
+            if (d.model == ISING) reduce_partials<ISING, 256>(d, t, d.rec_row0 + (int64_t)k);
+            else if (d.model == POTTS) reduce_partials<POTTS, 256>(d, t, d.rec_row0 + (int64_t)k);
+            else reduce_partials<XY, 256>(d, t, d.rec_row0 + (int64_t)k);
         }
         for (int h = tid; h < HB; h += 256) s_set[h] = EMPTY;
         if (tid == 0) s_n = 0;
