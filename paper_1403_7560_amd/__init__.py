@@ -41,6 +41,11 @@ class Record(ctypes.Structure):
                 ("mag2", ctypes.c_double), ("mx", ctypes.c_double), ("my", ctypes.c_double)]
 
 
+RECORD_DTYPE = np.dtype([("sweep", np.int64), ("energy", np.float64), ("mag", np.float64),
+                         ("mag2", np.float64), ("mx", np.float64), ("my", np.float64)])
+assert RECORD_DTYPE.itemsize == ctypes.sizeof(Record)
+
+
 class JobDesc(ctypes.Structure):
     _fields_ = [("model", ctypes.c_int), ("dim", ctypes.c_int), ("L", ctypes.c_int),
                 ("q", ctypes.c_int), ("beta", ctypes.c_double), ("seed", ctypes.c_uint64),
@@ -237,14 +242,18 @@ class Lattice:
         _check(lib().sw_set_measure(self.h, 1 if on else 0))
 
     def series(self, max_records=None):
-        n = max_records if max_records is not None else 1 << 30
-        # ask for the count first with a bounded buffer
-        cap = min(n, 1 << 22)
-        buf = (Record * cap)()
-        got = _check(lib().sw_series(self.h, buf, cap))
-        out = {k: np.array([getattr(buf[i], k) for i in range(got)])
-               for k in ("sweep", "energy", "mag", "mag2", "mx", "my")}
-        return out
+        """The recorded series, oldest first (at most max_records): a dict of
+        arrays sweep, energy, mag, mag2, mx, my."""
+        limit = max_records if max_records is not None else 1 << 40
+        cap = min(limit, 1024)
+        while True:  # a buffer that grows until the whole series fits
+            buf = (Record * cap)()
+            got = _check(lib().sw_series(self.h, buf, cap))
+            if got < cap or cap >= limit:
+                break
+            cap = min(limit, cap * 8)
+        a = np.frombuffer(buf, dtype=RECORD_DTYPE, count=got)
+        return {k: a[k].copy() for k in RECORD_DTYPE.names}
 
     def profile(self, level):
         """0 off; 1 time the bond kernel of every 16th sweep; 2 also its merge."""
