@@ -73,10 +73,10 @@ __global__ void __launch_bounds__(256) k_init(const InstDesc *__restrict__ descs
 // first, which removes most repeats without touching the set); the thread
 // that inserts a pair links it.  All face elements of the tile are loaded at
 // once, before any link, and a thread's links advance together
-// (gunion_batch).  NT threads per workgroup: 128 when a 2D tile has at most
-// 128 face elements (so that a CU holds twice the tiles), else 256.  The
-// first workgroups of a lattice also reduce the sweep's measurement
-// partials.
+// (gunion_batch).  NT = 256 threads per workgroup (128-thread workgroups for
+// the 2D tiles, twice the tiles per CU, were slower: the first workgroups'
+// reduction of the records lengthens).  The first workgroups of a lattice
+// also reduce the sweep's measurement partials.
 // ---------------------------------------------------------------------------
 template <int DIM, int EMAX, int NT>
 __global__ void __launch_bounds__(NT) k_merge(const InstDesc *__restrict__ descs,
@@ -278,7 +278,7 @@ static hipError_t merge_dispatch(int v, const InstDesc *dd, const int2 *tm, int 
 #define X(i, a, b, c, w)                                                                                   \
     if (v == i) {                                                                                          \
         constexpr int FT = (b) * (c) + (a) * (c) + (DIM == 3 ? (a) * (b) : 0);                            \
-        constexpr int NTM = (DIM == 2 && FT <= 128) ? 128 : 256;                                           \
+        constexpr int NTM = 256;                                                                           \
         hipLaunchKernelGGL((k_merge<DIM, (FT + NTM - 1) / NTM, NTM>), dim3(nt), dim3(NTM), 0, s, dd, tm, k); \
         return hipGetLastError();                                                                          \
     }
