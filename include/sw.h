@@ -324,7 +324,10 @@ typedef struct {
 
 /* Start a server whose resident lattices may use at most hbm_budget_bytes of
  * device memory and at most max_active jobs at once; chunk = sweeps per
- * scheduling tick.  NULL on error. */
+ * scheduling tick.  The device buffers of finished jobs are kept for the
+ * next admissions (no allocation or free per job), at most
+ * min(hbm_budget_bytes / 4, 4 GiB) of them beyond the budget; they are
+ * released by sw_server_destroy.  NULL on error. */
 sw_server sw_server_create(int64_t hbm_budget_bytes, int max_active, int chunk);
 
 /* Queue a job; returns its id (>= 0) or SW_E_*.  Jobs whose footprint exceeds

@@ -16,6 +16,7 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/sw.h"
@@ -93,6 +94,61 @@ int check_error_word(uint32_t *err)
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// Device memory a server recycles: the buffers of a retired job's lattice go
+// back to a free list and the next admissions take them, so that jobs come
+// and go without hipFree (which waits for the device) or hipMalloc.  A block
+// is reused for a request of up to 1/8 less than its size; the free list
+// holds at most `cap` bytes (the largest blocks are released beyond it).
+// Blocks return only once the work that used them has completed (a server
+// retires jobs between ticks).
+// ---------------------------------------------------------------------------
+struct DevicePool {
+    std::multimap<size_t, void *> free_blocks;  // size -> block
+    std::unordered_map<void *, size_t> sizes;   // every block the pool allocated
+    size_t cached = 0;
+    size_t cap = 0;
+
+    hipError_t get(void **p, size_t n)
+    {
+        n = std::max<size_t>(n, 256);
+        auto it = free_blocks.lower_bound(n);
+        if (it != free_blocks.end() && it->first <= n + n / 8) {
+            *p = it->second;
+            cached -= it->first;
+            free_blocks.erase(it);
+            return hipSuccess;
+        }
+        hipError_t e = hipMalloc(p, n);
+        if (e == hipSuccess) sizes[*p] = n;
+        return e;
+    }
+
+    void put(void *p)
+    {
+        if (!p) return;
+        auto s = sizes.find(p);
+        if (s == sizes.end()) {
+            (void)hipFree(p);
+            return;
+        }
+        free_blocks.emplace(s->second, p);
+        cached += s->second;
+        while (cached > cap && !free_blocks.empty()) {
+            auto big = std::prev(free_blocks.end());
+            cached -= big->first;
+            sizes.erase(big->second);
+            (void)hipFree(big->second);
+            free_blocks.erase(big);
+        }
+    }
+
+    ~DevicePool()
+    {
+        for (auto &kv : free_blocks) (void)hipFree(kv.second);
+    }
+};
+
+// ---------------------------------------------------------------------------
 // One lattice and its device buffers.
 // ---------------------------------------------------------------------------
 struct Lattice;
@@ -155,6 +211,23 @@ struct Lattice {
     std::vector<hipEvent_t> events;
     double prof_ms[3] = {0, 0, 0};
     int64_t prof_n[3] = {0, 0, 0};
+    // served lattices take their device buffers from the server's pool
+    DevicePool *pool = nullptr;
+
+    template <typename T>
+    hipError_t dmalloc(T **p, size_t n)
+    {
+        void *v = nullptr;
+        const hipError_t e = pool ? pool->get(&v, n) : hipMalloc(&v, n);
+        *p = (T *)v;
+        return e;
+    }
+    void dfree(void *p)
+    {
+        if (!p) return;
+        if (pool) pool->put(p);
+        else (void)hipFree(p);
+    }
 
     ~Lattice()
     {
@@ -176,8 +249,7 @@ struct Lattice {
     {
         void *ptrs[] = {state, label, label2, theta_w[0], theta_w[1], bond, face, part, rec, d_solo, d_tmap, err,
                         edges, ecount, rbuf, ctl, clock_thr, clock_trig};
-        for (void *p : ptrs)
-            if (p) (void)hipFree(p);
+        for (void *p : ptrs) dfree(p);
         state = nullptr;
         label = nullptr;
         label2 = nullptr;
@@ -293,7 +365,7 @@ struct Lattice {
             trig[k] = std::cos((TWO_PI_D_HOST * (double)k) / (double)q);
             trig[q + k] = std::sin((TWO_PI_D_HOST * (double)k) / (double)q);
         }
-        if (hipMalloc(&clock_thr, thr.size() * 4) != hipSuccess || hipMalloc(&clock_trig, trig.size() * 8) != hipSuccess)
+        if (dmalloc(&clock_thr, thr.size() * 4) != hipSuccess || dmalloc(&clock_trig, trig.size() * 8) != hipSuccess)
             return fail(SW_E_NOMEM, "clock table allocation failed");
         HIPCHK(hipMemcpy(clock_thr, thr.data(), thr.size() * 4, hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(clock_trig, trig.data(), trig.size() * 8, hipMemcpyHostToDevice));
@@ -313,17 +385,17 @@ struct Lattice {
             const int64_t T = (int64_t)ext[0] * ext[1] * ext[2];
             for (int mu = 0; mu < dim; ++mu)
                 if (tiles[mu] > 1) ec += (int)(T / ext[mu]);
-            if (!edges && hipMalloc(&edges, (size_t)ntiles * std::max(ec, 1) * 8) != hipSuccess)
+            if (!edges && dmalloc(&edges, (size_t)ntiles * std::max(ec, 1) * 8) != hipSuccess)
                 return fail(SW_E_NOMEM, "edge list allocation failed");
-            if (!ecount && hipMalloc(&ecount, (size_t)ntiles * 4) != hipSuccess)
+            if (!ecount && dmalloc(&ecount, (size_t)ntiles * 4) != hipSuccess)
                 return fail(SW_E_NOMEM, "edge count allocation failed");
-            if (alg == SW_LABEL_HAWICK && !rbuf && hipMalloc(&rbuf, (size_t)N * 4) != hipSuccess)
+            if (alg == SW_LABEL_HAWICK && !rbuf && dmalloc(&rbuf, (size_t)N * 4) != hipSuccess)
                 return fail(SW_E_NOMEM, "R allocation failed");
             const int words = label_ctl_words(cap);
             if (words > ctl_words) {
-                if (ctl) HIPCHK(hipFree(ctl));
+                dfree(ctl);
                 ctl = nullptr;
-                if (hipMalloc(&ctl, (size_t)words * 4) != hipSuccess) return fail(SW_E_NOMEM, "control words allocation failed");
+                if (dmalloc(&ctl, (size_t)words * 4) != hipSuccess) return fail(SW_E_NOMEM, "control words allocation failed");
                 ctl_words = words;
             }
             edge_cap = ec;
@@ -360,11 +432,11 @@ struct Lattice {
         if (need <= rec_cap) return SW_OK;
         int64_t cap = std::max<int64_t>(need, 2 * rec_cap);
         int64_t *p = nullptr;
-        if (hipMalloc(&p, (size_t)(cap + 1) * nslots * 8) != hipSuccess)
+        if (dmalloc(&p, (size_t)(cap + 1) * nslots * 8) != hipSuccess)
             return fail(SW_E_NOMEM, "record buffer allocation failed");
         if (rec && rec_count > 0)
             HIPCHK(hipMemcpy(p, rec, (size_t)rec_count * nslots * 8, hipMemcpyDeviceToDevice));
-        if (rec) HIPCHK(hipFree(rec));
+        dfree(rec);
         rec = p;
         rec_cap = cap;
         return SW_OK;
@@ -401,16 +473,16 @@ struct Lattice {
             face_off[mu] = face_total;
             if (mu < dim && tiles[mu] > 1) face_total += (int64_t)ntiles * 2 * face_len[mu];
         }
-        if (hipMalloc(&state, (size_t)N * state_bytes(model)) != hipSuccess ||
-            hipMalloc(&label, (size_t)N * 4) != hipSuccess || hipMalloc(&label2, (size_t)N * 4) != hipSuccess ||
-            hipMalloc(&bond, (size_t)N) != hipSuccess ||
-            (model >= XY && (hipMalloc(&theta_w[0], (size_t)N * state_bytes(model)) != hipSuccess ||
-                             hipMalloc(&theta_w[1], (size_t)N * state_bytes(model)) != hipSuccess)) ||
-            hipMalloc(&face, (size_t)std::max<int64_t>(face_total, 1) * 4) != hipSuccess ||
-            hipMalloc(&part, (size_t)ntiles * nslots * 8) != hipSuccess ||
-            hipMalloc(&d_solo, sizeof(InstDesc)) != hipSuccess ||
-            hipMalloc(&d_tmap, (size_t)ntiles * sizeof(int2)) != hipSuccess ||
-            hipMalloc(&err, 256) != hipSuccess) {
+        if (dmalloc(&state, (size_t)N * state_bytes(model)) != hipSuccess ||
+            dmalloc(&label, (size_t)N * 4) != hipSuccess || dmalloc(&label2, (size_t)N * 4) != hipSuccess ||
+            dmalloc(&bond, (size_t)N) != hipSuccess ||
+            (model >= XY && (dmalloc(&theta_w[0], (size_t)N * state_bytes(model)) != hipSuccess ||
+                             dmalloc(&theta_w[1], (size_t)N * state_bytes(model)) != hipSuccess)) ||
+            dmalloc(&face, (size_t)std::max<int64_t>(face_total, 1) * 4) != hipSuccess ||
+            dmalloc(&part, (size_t)ntiles * nslots * 8) != hipSuccess ||
+            dmalloc(&d_solo, sizeof(InstDesc)) != hipSuccess ||
+            dmalloc(&d_tmap, (size_t)ntiles * sizeof(int2)) != hipSuccess ||
+            dmalloc(&err, 256) != hipSuccess) {
             (void)hipGetLastError();
             return fail(SW_E_NOMEM, "device allocation failed");
         }
@@ -934,6 +1006,8 @@ struct ServerJob {
 };
 
 struct sw_server_s {
+    // first member: destroyed last, after every lattice has returned its blocks
+    DevicePool pool;
     int64_t budget = 0, used = 0;
     int max_active = 1;
     int chunk = 32;
@@ -962,8 +1036,7 @@ struct sw_server_s {
     ~sw_server_s()
     {
         for (hipStream_t st : streams) (void)hipStreamSynchronize(st);
-        for (Group &g : groups)
-            if (g.d_tmap) (void)hipFree(g.d_tmap);
+        for (Group &g : groups) pool.put(g.d_tmap);
         if (d_desc) (void)hipFree(d_desc);
         if (h_desc) (void)hipHostFree(h_desc);
         if (d_err) (void)hipFree(d_err);
@@ -977,8 +1050,7 @@ struct sw_server_s {
 
     int rebuild()
     {
-        for (Group &g : groups)
-            if (g.d_tmap) (void)hipFree(g.d_tmap);
+        for (Group &g : groups) pool.put(g.d_tmap);
         groups.clear();
         if ((int)active.size() > desc_cap) {
             if (d_desc) (void)hipFree(d_desc);
@@ -1009,8 +1081,10 @@ struct sw_server_s {
             g.nfull = (int)tm.size();
             tm.insert(tm.end(), cut.begin(), cut.end());
             g.ntiles = (int)tm.size();
-            if (hipMalloc(&g.d_tmap, tm.size() * sizeof(int2)) != hipSuccess)
+            void *tmv = nullptr;
+            if (pool.get(&tmv, tm.size() * sizeof(int2)) != hipSuccess)
                 return fail(SW_E_NOMEM, "tile map allocation failed");
+            g.d_tmap = (int2 *)tmv;
             HIPCHK(hipMemcpy(g.d_tmap, tm.data(), tm.size() * sizeof(int2), hipMemcpyHostToDevice));
         }
         // groups to parts: largest first, each to the part with the fewest sites
@@ -1110,6 +1184,7 @@ struct sw_server_s {
             std::unique_ptr<ServerJob> sj = std::move(queue.front());
             queue.pop_front();
             sj->lat.reset(new Lattice());
+            sj->lat->pool = &pool;
             const sw_job_desc &jd = sj->job.lattice;
             int rc = sj->lat->create(jd.model, jd.dim, jd.L, jd.q, jd.beta, jd.seed, jd.replica,
                                      tuned_tile(jd.model, jd.dim, jd.L), admit_stream);
@@ -1643,6 +1718,7 @@ sw_server sw_server_create(int64_t budget, int max_active, int chunk)
     s->budget = budget;
     s->max_active = max_active;
     s->chunk = chunk;
+    s->pool.cap = (size_t)std::min<int64_t>(budget / 4, (int64_t)4 << 30);
     for (int p = 0; p < SERVER_STREAMS; ++p) {
         hipStream_t st = make_stream();
         if (!st) {
