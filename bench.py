@@ -82,6 +82,15 @@ def merge_bytes_per_launch(lat):
     return 8 * lat.face_elements()
 
 
+def job_hbm(bond_bytes, seconds):
+    """Whole-job HBM figure of a form (plain, batched, served): the bond
+    kernel's algorithmic bytes of every sweep run (the dominant kernel; the
+    global phase and the flip add a few percent) over the wall time."""
+    gbs = bond_bytes / seconds / 1e9
+    return {"achieved_GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "bytes": "bond-kernel algorithmic bytes of every sweep / wall time"}
+
+
 def kernel_source_hash():
     h = hashlib.sha256()
     for f in ("sw_bond.h", "sw_device.h", "sw_internal.h"):
@@ -151,6 +160,7 @@ def served(n_jobs, rate, seed=2014, plain=True):
     from paper_1403_7560_amd import inputs
     jobs = inputs.job_mix(n_jobs, rate=rate, seed=seed)
     updates = sum(j["L"] ** j["dim"] * j["sweeps"] for j in jobs)
+    bond_bytes = sum(j["L"] ** j["dim"] * j["sweeps"] * algorithmic_bytes_per_site(j["model"]) for j in jobs)
     srv = sw.Server(96 << 30, max_active=256, chunk=32)
     lat_s = np.zeros(n_jobs)
     finish = np.zeros(n_jobs)
@@ -191,6 +201,7 @@ def served(n_jobs, rate, seed=2014, plain=True):
         "offered_load": round(offered, 2),
         # above 1 the queue grows over the trace: latencies then depend on its length
         "offered_over_served": round(offered / value, 3),
+        "job_hbm": job_hbm(bond_bytes, makespan),
         "plain_form": None, "speedup_vs_plain": None,
     }
     if plain:
@@ -201,7 +212,8 @@ def served(n_jobs, rate, seed=2014, plain=True):
             lat.close()
         plain_s = time.perf_counter() - t1
         pv = updates / (plain_s * 1e9)
-        out["plain_form"] = {"value": round(pv, 3), "seconds": round(plain_s, 2)}
+        out["plain_form"] = {"value": round(pv, 3), "seconds": round(plain_s, 2),
+                             "job_hbm": job_hbm(bond_bytes, plain_s)}
         out["speedup_vs_plain"] = round(value / pv, 3)
     return out
 
@@ -266,8 +278,9 @@ def leg_plain(sw, inputs, name, W, K, labeller=None):
     v, dt, kernels, lats = timed_plain(sw, lattices, W, K, labeller)
     for lat in lats:
         lat.close()
+    bond_bytes = sum(j["L"] ** j["dim"] * algorithmic_bytes_per_site(j["model"]) for j in lattices) * K
     return {"value": round(v, 3), "unit": "spin updates/ns", "ms_per_sweep": round(dt * 1e3 / K, 4),
-            "steps": K, "warmup": W, "kernels": kernels}
+            "steps": K, "warmup": W, "kernels": kernels, "job_hbm": job_hbm(bond_bytes, dt)}
 
 
 def update_only(sw, lattices, W, K):
@@ -289,8 +302,10 @@ def leg_batched(sw, inputs, name, W, K):
     dt = time.perf_counter() - t0
     b.close()
     total = sum(j["L"] ** j["dim"] for j in lattices) * K
+    bond_bytes = sum(j["L"] ** j["dim"] * algorithmic_bytes_per_site(j["model"]) for j in lattices) * K
     return {"value": round(total / (dt * 1e9), 3), "unit": "spin updates/ns",
-            "ms_per_step": round(dt * 1e3 / K, 4), "steps": K, "warmup": W, "lattices": len(lattices)}
+            "ms_per_step": round(dt * 1e3 / K, 4), "steps": K, "warmup": W, "lattices": len(lattices),
+            "job_hbm": job_hbm(bond_bytes, dt)}
 
 
 def to_json(out):
@@ -415,6 +430,7 @@ def main():
         "roofline": roof,
         "kernels": kernels,
         "cpu_baseline": cpu,
+        "job_hbm": job_hbm(sum(j["L"] ** j["dim"] * algorithmic_bytes_per_site(j["model"]) for j in lattices) * K, dt),
     }
     if args.config in PAPER_CONTEXT:
         out["paper_context"] = PAPER_CONTEXT[args.config]
@@ -439,7 +455,7 @@ def main():
             r = served(n_jobs, rate, plain=(tag == "at_200_per_s"))
             c5[tag] = {"value": round(r["value"], 3), "jobs": n_jobs, "rate_per_s": rate,
                        "latency_s": r["latency_s"], "offered_load": r["offered_load"],
-                       "offered_over_served": r["offered_over_served"]}
+                       "offered_over_served": r["offered_over_served"], "job_hbm": r["job_hbm"]}
             if r["plain_form"]:
                 c5[tag]["plain_form"] = r["plain_form"]
                 c5[tag]["speedup_vs_plain"] = r["speedup_vs_plain"]
