@@ -82,6 +82,25 @@ def merge_bytes_per_launch(lat):
     return 8 * lat.face_elements()
 
 
+def copy_probe(sw, nbytes):
+    """One device-to-device copy of nbytes (the runtime's copy kernel reads
+    and writes nbytes), for scaling the profiler's HBM byte counters.  It
+    goes through the HIP runtime the engine's library itself loaded (found
+    by its soname once the library is in), so that the probe and the
+    kernels it calibrates run on the same runtime."""
+    import ctypes
+    sw.lib()
+    hip = ctypes.CDLL("libamdhip64.so.7")
+    a, b = ctypes.c_void_p(), ctypes.c_void_p()
+    n = ctypes.c_size_t(nbytes)
+    for rc in (hip.hipMalloc(ctypes.byref(a), n), hip.hipMalloc(ctypes.byref(b), n),
+               hip.hipMemset(a, 1, n), hip.hipDeviceSynchronize(),
+               hip.hipMemcpy(b, a, n, 3),  # hipMemcpyDeviceToDevice
+               hip.hipDeviceSynchronize(), hip.hipFree(a), hip.hipFree(b)):
+        if rc != 0:
+            raise RuntimeError(f"copy probe: HIP error {rc}")
+
+
 def job_hbm(bond_bytes, seconds):
     """Whole-job HBM figure of a form (plain, batched, served): the bond
     kernel's algorithmic bytes of every sweep run (the dominant kernel; the
@@ -350,14 +369,7 @@ def main():
     import paper_1403_7560_amd as sw
 
     if args.copy_probe:
-        # a plain copy of known size: reads and writes copy_probe bytes, for
-        # scaling the HBM byte counters of the profiler
-        import torch
-        a = torch.ones(args.copy_probe // 4, dtype=torch.float32, device="cuda:0")
-        b = torch.empty_like(a)
-        b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
+        copy_probe(sw, args.copy_probe)
 
     if args.config == "C5":
         r = served(args.jobs, args.rate, plain=not args.no_plain)
