@@ -361,7 +361,7 @@ __device__ void reduce_partials(const InstDesc &d, int t, int64_t row)
 // Tile shapes: X(variant, TX, TY, TZ, wavefronts per workgroup).  The first
 // shape of each table is the fastest on large lattices (it is the default
 // unless it pads a small lattice much more than another shape).
-#define SW_VARIANTS_ISING2 X(0, 64, 64, 1, 4) X(1, 64, 32, 1, 4) X(2, 64, 128, 1, 8) X(3, 64, 256, 1, 16)
+#define SW_VARIANTS_ISING2 X(0, 64, 64, 1, 4) X(1, 64, 32, 1, 4) X(2, 64, 128, 1, 8) X(3, 64, 256, 1, 16) X(4, 64, 64, 1, 16)
 #define SW_VARIANTS_ISING3 X(0, 64, 8, 16, 8) X(1, 64, 8, 8, 4) X(2, 64, 4, 8, 4) X(3, 64, 16, 16, 16)
 #define SW_VARIANTS_XY2 X(0, 64, 32, 1, 4) X(1, 64, 16, 1, 4) X(2, 64, 64, 1, 8)
 #define SW_VARIANTS_XY3 X(0, 64, 4, 8, 4) X(1, 64, 8, 4, 4) X(2, 64, 8, 8, 8) X(3, 64, 8, 16, 16)

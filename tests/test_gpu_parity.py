@@ -7,9 +7,11 @@ are evaluated in the same order on both sides, so they are expected to agree
 bit for bit as well.
 
 Sizes span several tiles with a ragged tail (the default tiles are 64x64
-(Ising/Potts) and 64x32 (XY) in 2D, 64x8x8 and 64x4x8 in 3D) plus lattices
+(Ising/Potts) and 64x32 (XY) in 2D, 64x8x16 and 64x4x8 in 3D) plus lattices
 smaller than one tile, where the periodic wrap stays inside the tile; every
-other tile shape runs on ragged lattices too.
+other tile shape runs on ragged lattices too.  2D Ising/Potts launches of at
+most one 64x64 tile per CU run the 16-wavefront kernels of that tile; the
+1100 and 1030 cases have more tiles and run the 4-wavefront ones.
 """
 import math
 import sys
@@ -74,6 +76,10 @@ CASES = [
     (POTTS, 2, 45, 11, 0.7, 4),     # q = 11: the smallest q counted with LDS atomics
     (POTTS, 2, 70, 65, 0.5, 4),     # q > 64: state counts read from two wavefronts' queue memory
     (POTTS, 2, 130, 129, 0.45, 3),  # q > 128: and from three
+    # more 64x64 tiles than CUs: the 4-wavefront kernels (fewer run the
+    # 16-wavefront ones on the same tiles), here with tiles cut by the edge
+    (ISING, 2, 1100, 2, 2.269185, 3),
+    (POTTS, 2, 1030, 3, 0.994972861, 2),
     (POTTS, 3, 20, 129, 0.7, 3),
     (ISING, 3, 3, 2, 4.5115, 20),
     (ISING, 3, 33, 2, 4.5115, 5),
