@@ -272,6 +272,14 @@ k_bond(const InstDesc *__restrict__ descs,
     // clock: the paper's tables, cos (= the pair energy rule) and sin of 2 pi k / q
     __shared__ double s_trig[IS_CK ? 2 * CLOCK_QMAX : 1];
     __shared__ uint32_t s_axis[2];  // clock: this sweep's and the previous sweep's mirror axis
+    // 3D XY after the first sweep of a chain: the incoming angles of the sites
+    // outside a wavefront's rows that its bond tests read (slot j < R: +z of
+    // row j where the next plane is not the wavefront's; R + p: +y of plane
+    // p's last row; last: the halo column, lane c < R for row c), resolved
+    // in one batch before the wavefront's own rows
+    constexpr bool NBX = IS_XY && DIM == 3;
+    constexpr int NBS = R + R / TY + 1;
+    __shared__ float s_nth[NBX ? NW * NBS * 64 : 1];
 
     const int2 tm = tmap[tile_slot()];
     if (tm.x < 0) return;
@@ -480,11 +488,76 @@ k_bond(const InstDesc *__restrict__ descs,
         }
         __syncthreads();
     }
+    if constexpr (NBX) {
+        if (from_labels) {
+            // one batch: every slot's label word and angle, then their roots'
+            // words, chains walked in lock-step rounds, as for the own rows
+            uint32_t g[NBS], w[NBS], val[NBS];
+            float th[NBS];
+            bool use[NBS];
+            const int eyl = min(TY, ey) - 1;  // local y of a plane's last row
+#pragma unroll
+            for (int i = 0; i < NBS; ++i) {
+                use[i] = false;
+                g[i] = 0u;
+                if (i < R) {
+                    const int jf = i & ~3;
+                    if (!(jf + TY < R && row_z(jf) + 1 < ez) && vc && row_ok(i)) {
+                        use[i] = true;
+                        g[i] = gat(gx, row_y(i), row_z(i) + 1);
+                    }
+                } else if (i < R + R / TY) {
+                    const int j = (i - R) * TY + eyl;
+                    if (vc && row_ok(j)) {
+                        use[i] = true;
+                        g[i] = gat(gx, row_y(j) + 1, row_z(j));
+                    }
+                } else {
+                    const int ly = c % TY, lz = r0 / TY + c / TY;
+                    if (c < R && ly < ey && lz < ez) {
+                        use[i] = true;
+                        g[i] = gin(gxr, ly, lz);
+                    }
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < NBS; ++i) {
+                w[i] = use[i] ? lab_prev[g[i]] : ROOT_FLAG;
+                th[i] = use[i] ? th_prev[g[i]] : 0.0f;
+            }
+#pragma unroll
+            for (int i = 0; i < NBS; ++i) val[i] = (w[i] & ROOT_FLAG) ? w[i] : lab_prev[w[i]];
+            bool more = false;
+#pragma unroll
+            for (int i = 0; i < NBS; ++i) more |= !(val[i] & ROOT_FLAG);
+            uint32_t rounds = 0;
+            while (more) {
+                if (++rounds > d.walk_cap) {
+                    flag_error(d, ERR_WALK);
+#pragma unroll
+                    for (int i = 0; i < NBS; ++i)
+                        if (!(val[i] & ROOT_FLAG)) val[i] = ROOT_FLAG;
+                    break;
+                }
+                more = false;
+#pragma unroll
+                for (int i = 0; i < NBS; ++i)
+                    if (!(val[i] & ROOT_FLAG)) {
+                        val[i] = lab_prev[val[i]];
+                        more |= !(val[i] & ROOT_FLAG);
+                    }
+            }
+#pragma unroll
+            for (int i = 0; i < NBS; ++i)
+                if (use[i]) s_nth[(wv * NBS + i) * 64 + c] = (val[i] & 1u) ? xy_reflect(th[i], phi_prev) : th[i];
+        }
+    }
     if (from_labels) {
-        // per half of the rows: every row's label word, then all their tile
+        // per half of the rows (3D XY: all of them, its neighbour batch has
+        // freed its registers): every row's label word, then all their tile
         // roots' words, in flight together; chains the merge made longer walked
         // in lock-step rounds; the tile root pointed at the final root
-        constexpr int RH = (R >= 8) ? R / 2 : R;
+        constexpr int RH = (R >= 8 && !NBX) ? R / 2 : R;
 #pragma unroll
         for (int h = 0; h < R; h += RH) {
             uint32_t w[RH], cur[RH], val[RH];
@@ -624,7 +697,14 @@ k_bond(const InstDesc *__restrict__ descs,
     uint32_t hxg = 0;
     if (VEC && c < R) {
         const int ly = DIM == 2 ? r0 + c : c % TY, lz = DIM == 2 ? 0 : r0 / TY + c / TY;
-        if (ly < ey && lz < ez) hx = value_at(gin(gxr, ly, lz), hxS);
+        if (ly < ey && lz < ez) {
+            if constexpr (NBX) {
+                if (from_labels) xy_sincos(s_nth[(wv * NBS + NBS - 1) * 64 + c], s_cs, hx, hxS);
+                else hx = value_at(gin(gxr, ly, lz), hxS);
+            } else {
+                hx = value_at(gin(gxr, ly, lz), hxS);
+            }
+        }
     }
     if (!VEC && c < NG) {
         uint32_t hg[4];
@@ -820,7 +900,17 @@ k_bond(const InstDesc *__restrict__ descs,
                     zu[m] = vc && row_ok(jf + m);
                     zg[m] = zu[m] ? gat(gx, row_y(jf + m), row_z(jf + m) + 1) : 0u;
                 }
-                values4(zg, zu, zbuf, zbufS);
+                if constexpr (NBX) {
+                    if (from_labels) {
+#pragma unroll
+                        for (int m = 0; m < 4; ++m)
+                            if (zu[m]) xy_sincos(s_nth[(wv * NBS + jf + m) * 64 + c], s_cs, zbuf[m], zbufS[m]);
+                    } else {
+                        values4(zg, zu, zbuf, zbufS);
+                    }
+                } else {
+                    values4(zg, zu, zbuf, zbufS);
+                }
             }
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
@@ -835,7 +925,14 @@ k_bond(const InstDesc *__restrict__ descs,
                 } else {
                     up = 0;
                     upS = 0;
-                    if (vc) up = value_at(gat(gx, ly + 1, lz), upS);
+                    if (vc) {
+                        if constexpr (NBX) {
+                            if (from_labels) xy_sincos(s_nth[(wv * NBS + R + j / TY) * 64 + c], s_cs, up, upS);
+                            else up = value_at(gat(gx, ly + 1, lz), upS);
+                        } else {
+                            up = value_at(gat(gx, ly + 1, lz), upS);
+                        }
+                    }
                 }
                 V zn = 0, znS = 0;
                 if (DIM == 3) {

@@ -782,8 +782,8 @@ static std::map<std::tuple<int, int, int>, int> g_tuned;
 
 // Shape of a lattice nobody has tuned: the first of the table (the fastest on
 // large lattices) unless padding the lattice to whole tiles of it costs more
-// than a quarter over the shape that pads least.
-static int default_tile(int model, int dim, int L)
+// than sn/sd (a quarter) over the shape that pads least.
+static int default_tile(int model, int dim, int L, int64_t sn = 5, int64_t sd = 4)
 {
     auto padded = [&](int v) {
         const TileShape s = tile_shape(model, dim, v);
@@ -803,7 +803,7 @@ static int default_tile(int model, int dim, int L)
             best = v;
             pmin = padded(v);
         }
-    return padded(0) * 4 <= pmin * 5 ? 0 : best;
+    return padded(0) * sd <= pmin * sn ? 0 : best;
 }
 
 static int tuned_tile(int model, int dim, int L)
@@ -811,6 +811,18 @@ static int tuned_tile(int model, int dim, int L)
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tuned.find(std::make_tuple(model, dim, L));
     return it == g_tuned.end() ? default_tile(model, dim, L) : it->second;
+}
+
+// The same for a served job.  The server's launches cover many lattices and
+// fill the chip, and there the first shape is the fastest per padded site
+// (the 300-job served mix ran at 55.8 updates/ns against 54.9 under the rule
+// above): it gives way only to a shape that pads the lattice to under two
+// thirds as many sites.
+static int served_tile(int model, int dim, int L)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(std::make_tuple(model, dim, L));
+    return it == g_tuned.end() ? default_tile(model, dim, L, 3, 2) : it->second;
 }
 
 // ---------------------------------------------------------------------------
@@ -1218,7 +1230,7 @@ struct sw_server_s {
             sj->lat->pool = &pool;
             const sw_job_desc &jd = sj->job.lattice;
             int rc = sj->lat->create(jd.model, jd.dim, jd.L, jd.q, jd.beta, jd.seed, jd.replica,
-                                     tuned_tile(jd.model, jd.dim, jd.L), admit_stream);
+                                     served_tile(jd.model, jd.dim, jd.L), admit_stream);
             if (rc == SW_OK) rc = sj->lat->grow_records(sj->job.sweeps);
             if (rc) {
                 sw_job_result r;
