@@ -327,8 +327,9 @@ static int device_cus()
 // 2D Ising/Potts shape 0 (64x64 tiles, 4 wavefronts) runs the 16-wavefront
 // kernels of the same tile (shape 4) when the launch covers at most one tile
 // per CU: such a launch cannot fill the GPU, and the shorter work per
-// wavefront lowers its latency (L = 64: 17.0 -> 10.7 us per sweep; L = 1024:
-// 34.8 -> 27.0; from 1.5 tiles per CU on the 4-wavefront kernel is faster).
+// wavefront lowers its latency (2D Ising, us per sweep: L = 64 17.0 -> 10.7;
+// L = 1024, one tile per CU, 34.8 -> 27.0; at L = 1536, 2.25 tiles per CU,
+// the 4-wavefront kernel is the faster, 39.9 against 42.4).
 // The tiles, and so the trajectory, are the same.
 static int launch_variant(int model, int dim, int v, int nt)
 {
