@@ -466,25 +466,25 @@ k_bond(const InstDesc *__restrict__ descs,
     // overwrites them at its end, while neighbours may already have rewritten
     // theirs.
     if (DIM == 2 && from_labels && (d.tiles[0] > 1 || d.tiles[1] > 1)) {
-#pragma unroll
-        for (int mu = 0; mu < 2; ++mu) {
-            if (d.tiles[mu] == 1) continue;  // uniform
-            const int F = d.face_len[mu];
-            const GLOBAL int32_t *fs = (const GLOBAL int32_t *)d.face + d.face_off[mu] + (int64_t)t * 2 * F;
-            for (int e0 = 0; e0 < 2 * F; e0 += NT) {
-                const int e = e0 + tid;
-                const int32_t x = e < 2 * F ? fs[e] : -1;
-                const int32_t xl = (int32_t)from_left((uint32_t)x);
-                if (x < 0 || (c != 0 && xl == x)) continue;  // no root, or the lane before has it
-                uint32_t r = (uint32_t)x, w = lab_prev[r], steps = 0;
-                while (!(w & ROOT_FLAG)) {
-                    if (++steps > d.walk_cap) break;
-                    r = w;
-                    w = lab_prev[r];
-                }
-                if (!(w & ROOT_FLAG)) flag_error(d, ERR_WALK);
-                else if (r != (uint32_t)x) lab_prev[x] = r;
+        // both faces' slots in one pass (the x face's, then the y face's): a
+        // 64x64 tile's 256 slots are one per thread, walked side by side
+        const int E0 = d.tiles[0] > 1 ? 2 * d.face_len[0] : 0;
+        const int E = E0 + (d.tiles[1] > 1 ? 2 * d.face_len[1] : 0);
+        const GLOBAL int32_t *fs0 = (const GLOBAL int32_t *)d.face + d.face_off[0] + (int64_t)t * 2 * d.face_len[0];
+        const GLOBAL int32_t *fs1 = (const GLOBAL int32_t *)d.face + d.face_off[1] + (int64_t)t * 2 * d.face_len[1];
+        for (int e0 = 0; e0 < E; e0 += NT) {
+            const int e = e0 + tid;
+            const int32_t x = e < E0 ? fs0[e] : (e < E ? fs1[e - E0] : -1);
+            const int32_t xl = (int32_t)from_left((uint32_t)x);
+            if (x < 0 || (c != 0 && xl == x)) continue;  // no root, or the lane before has it
+            uint32_t r = (uint32_t)x, w = lab_prev[r], steps = 0;
+            while (!(w & ROOT_FLAG)) {
+                if (++steps > d.walk_cap) break;
+                r = w;
+                w = lab_prev[r];
             }
+            if (!(w & ROOT_FLAG)) flag_error(d, ERR_WALK);
+            else if (r != (uint32_t)x) lab_prev[x] = r;
         }
         __syncthreads();
     }
