@@ -477,10 +477,19 @@ k_bond(const InstDesc *__restrict__ descs,
             const int32_t x = e < E0 ? fs0[e] : (e < E ? fs1[e - E0] : -1);
             const int32_t xl = (int32_t)from_left((uint32_t)x);
             if (x < 0 || (c != 0 && xl == x)) continue;  // no root, or the lane before has it
+            // path halving: each node passed is pointed at its grandparent,
+            // shortening the chains later workgroups and the chase walk
             uint32_t r = (uint32_t)x, w = lab_prev[r], steps = 0;
             while (!(w & ROOT_FLAG)) {
                 if (++steps > d.walk_cap) break;
-                r = w;
+                const uint32_t w2 = lab_prev[w];
+                if (w2 & ROOT_FLAG) {
+                    r = w;
+                    w = w2;
+                    break;
+                }
+                lab_prev[r] = w2;
+                r = w2;
                 w = lab_prev[r];
             }
             if (!(w & ROOT_FLAG)) flag_error(d, ERR_WALK);
