@@ -766,16 +766,19 @@ k_bond(const InstDesc *__restrict__ descs,
 #pragma unroll
             for (int gi = 0; gi < HG; ++gi) s_par[TX * (r0 - R) + TX * gi + c] = (int)P[gi];
         }
-        // a full tile: the last wavefront's +z plane is the next tile's first
-        // plane; every wavefront resolves rows of it (ly = wv, wv + NW, ...)
-        // into the last wavefront's hand-over slots, byte ly % 4 of word ly / 4,
-        // instead of the last wavefront loading them all while the others
-        // wait for it at the next barrier
-        if constexpr (HAND && FULL) {
-            typedef __attribute__((address_space(3))) uint8_t lds_u8;
-            lds_u8 *last = (lds_u8 *)&s_par[TX * (R * (NW - 1))];
-            for (int ly = wv; ly < TY; ly += NW)
-                last[4 * (TX * (ly / 4) + c) + (ly % 4)] = (uint8_t)state_byte(gat(gx, ly, TZ));
+        // a tile with all TZ planes: the last wavefront's +z plane is the next
+        // tile's first plane; every wavefront resolves rows of it (ly = wv,
+        // wv + NW, ...) into the last wavefront's hand-over slots, byte ly % 4
+        // of word ly / 4, instead of the last wavefront loading them all while
+        // the others wait for it at the next barrier
+        if constexpr (HAND) {
+            if (ez == TZ) {  // uniform
+                typedef __attribute__((address_space(3))) uint8_t lds_u8;
+                lds_u8 *last = (lds_u8 *)&s_par[TX * (R * (NW - 1))];
+                for (int ly = wv; ly < TY; ly += NW)
+                    last[4 * (TX * (ly / 4) + c) + (ly % 4)] =
+                        (vc && ly < ey) ? (uint8_t)state_byte(gat(gx, ly, TZ)) : (uint8_t)0;
+            }
         }
         if (HAND) __syncthreads();
     }
@@ -835,7 +838,7 @@ k_bond(const InstDesc *__restrict__ descs,
                     PZ = P[gi + TY / 4 < NG ? gi + TY / 4 : gi];
                 } else if (HAND && lz + 1 < TZ && lz + 1 < ez) {
                     PZ = handed((jf % TY) / 4);  // the first plane of wavefront wv + 1
-                } else if (HAND && FULL && lz + 1 == TZ) {
+                } else if (HAND && lz + 1 == TZ && ez == TZ) {
                     PZ = handed((jf % TY) / 4);  // the next tile's first plane, resolved by every wavefront
                 } else if (vc) {
                     uint32_t zg[4];
