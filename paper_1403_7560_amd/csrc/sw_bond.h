@@ -71,15 +71,6 @@ __device__ __forceinline__ double from_right_d(double v)
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-// A value every lane holds alike, moved to scalar registers.
-__device__ __forceinline__ double uniform_d(double v)
-{
-    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(u >> 32));
-    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
-
 __device__ __forceinline__ double readlane_d(double v, int l)
 {
     const unsigned long long u = (unsigned long long)__double_as_longlong(v);
@@ -238,12 +229,9 @@ __device__ __forceinline__ uint32_t clock_bond(uint32_t pi, uint32_t pj, uint32_
 // Wavefronts per SIMD the bond kernel's registers are sized for: Ising /
 // Potts the hardware's 8 while a wavefront holds at most 16 rows (the LDS
 // of 8 such wavefronts per SIMD fits the CU's 160 KB), else 3; XY keeps its
-// FP64 projections in registers and runs 5, spilling some of them to scratch:
-// the kernel waits on dependent label loads more than it issues, and the
-// fifth wavefront hides more of them than the spills cost (served job mix
-// 56.3 -> 57.1 spin updates/ns against 4 wavefronts without spills).
+// FP64 projections in registers and runs 4.
 template <int MODEL, int T, int NW> struct BondOccupancy {
-    static constexpr int value = (MODEL == XY) ? 5 : ((T / NW <= 1024) ? 8 : 3);
+    static constexpr int value = (MODEL == XY) ? 4 : ((T / NW <= 1024) ? 8 : 3);
 };
 // (the clock model keeps integer states and runs 8, like Ising)
 
@@ -401,10 +389,8 @@ k_bond(const InstDesc *__restrict__ descs,
         }
     }
     if (VEC || (MODEL == POTTS && meas)) __syncthreads();
-    // uniform over the workgroup: held in scalar registers
-    const double phi = IS_XY ? uniform_d(s_phi[0]) : 0.0, cphi = IS_XY ? uniform_d(s_phi[1]) : 0.0,
-                 sphi = IS_XY ? uniform_d(s_phi[2]) : 0.0;
-    const double phi_prev = IS_XY ? uniform_d(s_phi[3]) : 0.0;
+    const double phi = IS_XY ? s_phi[0] : 0.0, cphi = IS_XY ? s_phi[1] : 0.0, sphi = IS_XY ? s_phi[2] : 0.0;
+    const double phi_prev = IS_XY ? s_phi[3] : 0.0;
     const uint32_t axis = IS_CK ? s_axis[0] : 0u, axis_prev = IS_CK ? s_axis[1] : 0u;
     const uint32_t uq = (uint32_t)d.q;
 
